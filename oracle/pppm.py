@@ -1,0 +1,198 @@
+"""Plain FP64 NumPy PPPM with ik-differentiation: the ORACLE of the mesh method.
+
+TEST INFRASTRUCTURE ONLY: used by tests, the smoke check and the benchmark's
+CPU baseline, never by the GPU product path, and it shares no code with it.
+
+The paper computes the Gaussian-charge energy E_Gt (DPLR background section,
+the reciprocal sum over m != 0 with S(m) over ions and Wannier centroids) by
+PPPM with the Poisson-IK scheme of Hockney and Eastwood (Optimization section,
+hardware-offloaded 3D FFT: one forward and three inverse 3D FFTs).  The paper
+does not print the scheme's formulas; this module follows the standard
+particle-mesh method in its order:
+
+ 1. mesh coordinates u = r / h (h = L/K per axis), wrapped into [0, K);
+ 2. charge assignment with the cardinal B-spline M_p of order p, centred:
+        Q(g) = sum_j q_j prod_a M_p(u_ja - g_a + p/2)   (periodic in g);
+ 3. forward DFT  Q^(n) = sum_g Q(g) exp(-2 pi i n.g/K);
+ 4. the optimal influence function for ik-differentiation,
+        G(k) = sum_m (k . k_m) U^2(k_m) phi(k_m) / ( |k|^2 [sum_m U^2(k_m)]^2 ),
+    k = 2 pi n / L, k_m = k + 2 pi m / h, U(k) = prod_a sinc(k_a h_a/2)^p,
+    phi(k) = 4 pi exp(-k^2/(4 beta^2)) / k^2 (the Fourier transform of the
+    Gaussian-screened Coulomb kernel), alias sum |m_a| <= alias, G(0) = 0;
+ 5. energy  E = k_e/(2V) sum_{n != 0} G(n) |Q^(n)|^2;
+ 6. field spectra  E^_a(n) = -i k'_a G(n) Q^(n), with k'_a = 0 on the Nyquist
+    index n_a = -K_a/2 (its derivative has no real representation);
+ 7. three inverse DFTs without normalisation  E_a(g) = sum_n E^_a(n) exp(+2 pi i n.g/K);
+ 8. force interpolation with the same assignment function
+        F_ja = (k_e q_j / V) sum_g prod_b M_p(u_jb - g_b + p/2) E_a(g);
+ 9. virial  W_ab = k_e/(2V) sum_{n != 0} G |Q^|^2 [delta_ab - 2 (1 + k^2/(4 beta^2)) k_a k_b / k^2].
+
+With k = 2 pi m the factor phi/(2V) equals the paper's exp(-pi^2 m^2/beta^2) /
+(2 pi V m^2), so as h -> 0 this converges to the direct Ewald sum.
+Everything here uses full (not half) spectra and numpy.fft.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def bspline(p: int, x):
+    """Cardinal B-spline M_p(x) on [0, p] by the textbook recursion
+    M_1 = 1 on [0, 1), M_p(x) = [x M_{p-1}(x) + (p - x) M_{p-1}(x - 1)] / (p - 1)."""
+    x = np.asarray(x, dtype=np.float64)
+    if p == 1:
+        return ((x >= 0.0) & (x < 1.0)).astype(np.float64)
+    return (x * bspline(p - 1, x) + (p - x) * bspline(p - 1, x - 1.0)) / (p - 1)
+
+
+def stencil(u, p: int):
+    """Assignment stencil along one axis: the p mesh points g = s..s+p-1 with
+    s = floor(u - p/2) + 1 (those with |u - g| < p/2) and their weights
+    M_p(u - g + p/2).  Returns (g [n, p] int (unwrapped), w [n, p])."""
+    u = np.asarray(u, dtype=np.float64)
+    s = np.floor(u - p / 2.0).astype(np.int64) + 1
+    g = s[:, None] + np.arange(p)[None, :]
+    w = bspline(p, u[:, None] - g + p / 2.0)
+    return g, w
+
+
+def mesh_coords(pos, box, K):
+    """u = r / h wrapped into [0, K) per axis."""
+    pos = np.asarray(pos, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    K = np.asarray(K)
+    u = pos / (box / K)
+    u = np.mod(u, K)
+    return np.where(u >= K, 0.0, u)
+
+
+def spread(pos, q, box, K, p: int):
+    """Charge mesh Q[Kx, Ky, Kz] (index order x, y, z)."""
+    K = tuple(int(k) for k in K)
+    u = mesh_coords(pos, box, K)
+    q = np.asarray(q, dtype=np.float64)
+    st = [stencil(u[:, a], p) for a in range(3)]
+    Q = np.zeros(K[0] * K[1] * K[2])
+    for tx in range(p):
+        gx = np.mod(st[0][0][:, tx], K[0])
+        wx = q * st[0][1][:, tx]
+        for ty in range(p):
+            gy = np.mod(st[1][0][:, ty], K[1])
+            wxy = wx * st[1][1][:, ty]
+            for tz in range(p):
+                gz = np.mod(st[2][0][:, tz], K[2])
+                idx = (gx * K[1] + gy) * K[2] + gz
+                Q += np.bincount(idx, weights=wxy * st[2][1][:, tz], minlength=Q.size)
+    return Q.reshape(K)
+
+
+def interpolate(pos, box, K, p: int, field):
+    """sum_g W(u_j - g) field(g) for every particle j (same W as spread)."""
+    K = tuple(int(k) for k in K)
+    u = mesh_coords(pos, box, K)
+    st = [stencil(u[:, a], p) for a in range(3)]
+    out = np.zeros(u.shape[0])
+    flat = field.reshape(-1)
+    for tx in range(p):
+        gx = np.mod(st[0][0][:, tx], K[0])
+        wx = st[0][1][:, tx]
+        for ty in range(p):
+            gy = np.mod(st[1][0][:, ty], K[1])
+            wxy = wx * st[1][1][:, ty]
+            for tz in range(p):
+                gz = np.mod(st[2][0][:, tz], K[2])
+                out += wxy * st[2][1][:, tz] * flat[(gx * K[1] + gy) * K[2] + gz]
+    return out
+
+
+def wavevectors(box, K):
+    """Signed integer indices n (numpy.fft order; the Nyquist index is -K/2)
+    and k = 2 pi n / L per axis."""
+    n = [np.fft.fftfreq(int(K[a]), 1.0 / int(K[a])) for a in range(3)]
+    k = [2.0 * math.pi * n[a] / float(box[a]) for a in range(3)]
+    return n, k
+
+
+def influence(box, K, beta: float, p: int, alias: int = 2):
+    """Optimal ik influence function G on the full signed grid [Kx, Ky, Kz]."""
+    box = np.asarray(box, dtype=np.float64)
+    K = [int(k) for k in K]
+    h = box / np.asarray(K)
+    n, k = wavevectors(box, K)
+    kx, ky, kz = np.meshgrid(k[0], k[1], k[2], indexing="ij")
+    num = np.zeros(kx.shape)
+    den = np.zeros(kx.shape)
+    for mx in range(-alias, alias + 1):
+        kmx = kx + 2 * math.pi * mx / h[0]
+        ux = np.sinc(n[0] / K[0] + mx) ** (2 * p)
+        for my in range(-alias, alias + 1):
+            kmy = ky + 2 * math.pi * my / h[1]
+            uy = np.sinc(n[1] / K[1] + my) ** (2 * p)
+            for mz in range(-alias, alias + 1):
+                kmz = kz + 2 * math.pi * mz / h[2]
+                uz = np.sinc(n[2] / K[2] + mz) ** (2 * p)
+                u2 = ux[:, None, None] * uy[None, :, None] * uz[None, None, :]
+                km2 = kmx * kmx + kmy * kmy + kmz * kmz
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    phi = np.where(km2 > 0, 4 * math.pi * np.exp(-km2 / (4 * beta * beta)) / km2, 0.0)
+                num += (kx * kmx + ky * kmy + kz * kmz) * u2 * phi
+                den += u2
+    k2 = kx * kx + ky * ky + kz * kz
+    with np.errstate(divide="ignore", invalid="ignore"):
+        G = np.where(k2 > 0, num / (k2 * den * den), 0.0)
+    return G
+
+
+def pppm(pos, q, box, K, p: int, beta: float, ke: float, alias: int = 2, G=None,
+         return_parts: bool = False):
+    """PPPM-ik energy, forces [n,3] and virial [6] (xx,yy,zz,xy,xz,yz)."""
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    q = np.asarray(q, dtype=np.float64).reshape(-1)
+    box = np.asarray(box, dtype=np.float64).reshape(3)
+    K = [int(k) for k in K]
+    V = float(np.prod(box))
+    Q = spread(pos, q, box, K, p)
+    Qh = np.fft.fftn(Q)
+    if G is None:
+        G = influence(box, K, beta, p, alias)
+    n, k = wavevectors(box, K)
+    kg = np.meshgrid(k[0], k[1], k[2], indexing="ij")
+    s2 = (Qh.conj() * Qh).real
+    E = ke / (2 * V) * float((G * s2).sum())
+    k2 = kg[0] ** 2 + kg[1] ** 2 + kg[2] ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        c = np.where(k2 > 0, 2 * (1 + k2 / (4 * beta * beta)) / k2, 0.0)
+    W = np.empty(6)
+    for i, (a, b) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        W[i] = ke / (2 * V) * float((G * s2 * ((1.0 if a == b else 0.0) - c * kg[a] * kg[b])).sum())
+    ntot = K[0] * K[1] * K[2]
+    F = np.zeros_like(pos)
+    fields = []
+    for a in range(3):
+        kd = np.where(n[a] == -K[a] // 2, 0.0, k[a]) if K[a] % 2 == 0 else k[a]
+        shape = [1, 1, 1]
+        shape[a] = K[a]
+        Eh = -1j * kd.reshape(shape) * G * Qh
+        Ea = np.fft.ifftn(Eh) * ntot
+        fields.append(Ea.real)
+        F[:, a] = ke * q / V * interpolate(pos, box, K, p, Ea.real)
+    if return_parts:
+        return E, F, W, dict(Q=Q, Qhat=Qh, G=G, fields=fields)
+    return E, F, W
+
+
+def system_pppm(sys, K, p: int, beta: float, ke: float, alias: int = 2, G=None):
+    """pppm() on a systems.System; returns (E, F_ion, F_wc, W)."""
+    if np.isscalar(K):
+        K = (int(K),) * 3
+    E, F, W = pppm(sys.all_pos(), sys.all_q(), sys.box, K, p, beta, ke, alias, G)
+    return E, F[: sys.n_ion], F[sys.n_ion:], W
+
+
+def rel_rmse(F, Fref) -> float:
+    """||F - Fref||_2 / ||Fref||_2 over all components."""
+    F = np.asarray(F, dtype=np.float64)
+    Fref = np.asarray(Fref, dtype=np.float64)
+    return float(np.linalg.norm(F - Fref) / np.linalg.norm(Fref))
