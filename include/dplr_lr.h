@@ -1,0 +1,174 @@
+/*
+ * dplr_lr.h - C ABI of the MI355X (gfx950) DPLR long-range electrostatic step.
+ *
+ * The library evaluates the Gaussian-charge long-range energy of Deep Potential
+ * Long-Range (paper: DPLR background section, the energy E_Gt and structure
+ * factor S(m) equations) by particle-particle particle-mesh (PPPM) with
+ * ik-differentiation ("Poisson-IK", Optimization section, hardware-offloaded
+ * 3D FFT: one forward and three inverse 3D FFTs), times the Coulomb constant:
+ *
+ *   E = k_e/(2 pi V) sum_{m != 0} exp(-pi^2 m^2/beta^2)/m^2 |S(m)|^2,
+ *   S(m) = sum_i q_i exp(-2 pi i m.R_i) + sum_n q_n exp(-2 pi i m.W_n),
+ *
+ * where R_i are ion (atom) positions and W_n Wannier-centroid (WC) positions.
+ * It returns E, the forces on ions and on WCs separately (the two derivative
+ * terms dE_Gt/dR_i and dE_Gt/dW_n of the force chain-rule equations), and the
+ * virial.  Every step runs in the library's own HIP kernels; callers provide
+ * device memory and a HIP stream.
+ *
+ * Conventions
+ *   - Units: Angstrom, elementary charge, eV (k_e = 14.399645 eV A gives eV).
+ *   - Box: orthorhombic, edge lengths L[3]; positions may lie anywhere (they
+ *     are wrapped into the box).  The m = 0 term is excluded (tin-foil
+ *     boundary); a non-neutral input is computed as given.
+ *   - Arrays: positions and forces are contiguous [n][3] (x, y, z), charges
+ *     [n]; element type float for DPLR_LR_FP32 plans and double for
+ *     DPLR_LR_FP64 plans.  Energy and virial are always double.
+ *   - Virial order: xx, yy, zz, xy, xz, yz; W_ab = -dE/d(strain_ab).
+ *   - Every call is asynchronous on the plan's stream (no host
+ *     synchronisation, no device-to-host copy).  Device pointers must stay
+ *     valid until the stream has executed the call.  The library never frees
+ *     or keeps caller memory.
+ *   - One plan must not be used from two host threads, or on two streams, at
+ *     the same time (its workspace is shared by its calls).
+ *
+ * Errors
+ *   Every entry point validates its arguments on the host before it enqueues
+ *   any device work; on an error it returns a status code, leaves all outputs
+ *   untouched and records a message for dplr_lr_last_error().
+ */
+#ifndef DPLR_LR_H
+#define DPLR_LR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPLR_LR_ABI_VERSION 1
+
+typedef struct dplr_lr_plan_s* dplr_lr_plan;
+
+typedef enum {
+  DPLR_LR_OK = 0,
+  DPLR_LR_E_INVALID = 1,      /* bad argument (null pointer, negative size, ...) */
+  DPLR_LR_E_UNSUPPORTED = 2,  /* valid request outside what this build supports  */
+  DPLR_LR_E_NO_BOX = 3,       /* compute before set_box                          */
+  DPLR_LR_E_CAPACITY = 4,     /* more particles than the plan's capacity         */
+  DPLR_LR_E_DEVICE = 5,       /* a HIP runtime call failed                       */
+  DPLR_LR_E_NOMEM = 6         /* device or host allocation failed                */
+} dplr_lr_status;
+
+typedef enum { DPLR_LR_FP32 = 0, DPLR_LR_FP64 = 1 } dplr_lr_precision;
+
+/* flags */
+#define DPLR_LR_ACCUMULATE 0x1u   /* add forces into the output arrays instead of overwriting */
+#define DPLR_LR_NO_VIRIAL  0x2u   /* skip the virial reduction (virial6 may be NULL)         */
+
+typedef struct {
+  int32_t mesh[3];     /* Kx, Ky, Kz: powers of two in [16, 512]                          */
+  int32_t order;       /* B-spline assignment order p (points per axis), 2..8             */
+  double beta;         /* Gaussian width parameter beta of the E_Gt equation (1/A), > 0  */
+  double coulomb_k;    /* Coulomb constant k_e (eV A); E is returned in its units         */
+  int32_t precision;   /* dplr_lr_precision of spreading, FFTs and gather; the influence
+                          table and the energy/virial reductions are FP64 in both modes  */
+  int32_t alias_range; /* |m_a| <= alias_range in the influence-function alias sums, 0..4 */
+  int64_t capacity;    /* maximum n_ion + n_wc per call, 0 .. 2^31 - 1                    */
+  uint32_t flags;      /* DPLR_LR_ACCUMULATE | DPLR_LR_NO_VIRIAL                          */
+} dplr_lr_config;
+
+/* Version of this ABI (DPLR_LR_ABI_VERSION of the built library). */
+int32_t dplr_lr_abi_version(void);
+
+/* Fill *cfg with the defaults: mesh 32^3, order 5, beta 0.4, k_e 14.399645,
+ * FP32, alias range 2, capacity 0, no flags. */
+void dplr_lr_config_default(dplr_lr_config* cfg);
+
+/* Host-only validation of a configuration (no device call).  On failure a
+ * message is written to msg (NUL-terminated, at most msg_len bytes) when msg
+ * is not NULL. */
+dplr_lr_status dplr_lr_config_validate(const dplr_lr_config* cfg, char* msg, int64_t msg_len);
+
+/* Create a plan: validates cfg, then allocates the device workspace on the
+ * current HIP device.  hip_stream is a hipStream_t (NULL = the null stream).
+ * On success *out owns the workspace until dplr_lr_plan_destroy.  On failure
+ * *out is set to NULL and dplr_lr_last_error(NULL) holds the message. */
+dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, dplr_lr_plan* out);
+
+/* Rebind the plan to another stream (hipStream_t). */
+dplr_lr_status dplr_lr_set_stream(dplr_lr_plan p, void* hip_stream);
+
+/* Set the orthorhombic box (host array of 3 positive lengths, Angstrom) and
+ * enqueue the FP64 influence-function table for it: the optimal ik influence
+ * function of Hockney and Eastwood for the Gaussian-screened Coulomb kernel
+ * 4 pi exp(-k^2/4 beta^2)/k^2 (the Fourier form of the E_Gt summand) with
+ * B-spline assignment of the plan's order. */
+dplr_lr_status dplr_lr_set_box(dplr_lr_plan p, const double box_len[3]);
+
+/* The long-range step.  Device inputs: ion_pos [n_ion][3], ion_q [n_ion],
+ * wc_pos [n_wc][3], wc_q [n_wc] (plan precision).  Device outputs:
+ * ion_force [n_ion][3] and wc_force [n_wc][3] (F = -dE/dr, eV/A, plan
+ * precision), energy (1 double, eV) and virial6 (6 doubles, eV; may be NULL,
+ * and must be NULL-tolerant only when the plan has DPLR_LR_NO_VIRIAL).
+ * Pointers of an empty set (n = 0) may be NULL.  Requires set_box first and
+ * n_ion + n_wc <= capacity. */
+dplr_lr_status dplr_lr_compute_energy_forces_virial(
+    dplr_lr_plan p,
+    int64_t n_ion, const void* ion_pos, const void* ion_q,
+    int64_t n_wc, const void* wc_pos, const void* wc_q,
+    void* ion_force, void* wc_force, double* energy, double* virial6);
+
+/* Backward of the energy with respect to positions (the derivative the
+ * force chain-rule equations take of E_Gt): ion_grad = -g * ion_force and
+ * wc_grad = -g * wc_force, with g = *grad_energy (a device double, the
+ * incoming gradient of E).  Arrays as in compute; outputs may alias their
+ * inputs. */
+dplr_lr_status dplr_lr_scale_grad(dplr_lr_plan p, const double* grad_energy,
+                                  int64_t n_ion, const void* ion_force, void* ion_grad,
+                                  int64_t n_wc, const void* wc_force, void* wc_grad);
+
+/* Release the plan and its workspace (synchronises the plan's stream). NULL is accepted. */
+dplr_lr_status dplr_lr_plan_destroy(dplr_lr_plan p);
+
+/* Message of the last failed call on p (p = NULL: the last failed plan
+ * creation or validation of this thread).  Valid until the next call on p. */
+const char* dplr_lr_last_error(dplr_lr_plan p);
+
+/* Device bytes held by the plan's workspace. */
+int64_t dplr_lr_workspace_bytes(dplr_lr_plan p);
+
+/* Intermediate buffers of the most recent compute (for kernel-level tests):
+ *   DPLR_LR_BUF_SPECTRUM  the charge mesh transformed along x (real to
+ *                         complex) and y; the z transform is done inside
+ *                         the Poisson pass.  complex [Kx/2+1][Kz][Ky]
+ *                         (kx slowest, y fastest);
+ *   DPLR_LR_BUF_INFLUENCE FP64 influence table G(|nx|,|ny|,|nz|),
+ *                         [Kx/2+1][Ky/2+1][Kz/2+1];
+ *   DPLR_LR_BUF_FIELD_SPECTRA after the inverse z and y transforms,
+ *                         complex [3][Kx/2+1][Kz][Ky].
+ * Copies `bytes` bytes (at most the buffer size, else E_INVALID) into the
+ * device pointer dst, stream-ordered. */
+#define DPLR_LR_BUF_SPECTRUM 0
+#define DPLR_LR_BUF_INFLUENCE 1
+#define DPLR_LR_BUF_FIELD_SPECTRA 2
+dplr_lr_status dplr_lr_debug_copy(dplr_lr_plan p, int32_t which, void* dst, int64_t bytes);
+int64_t dplr_lr_debug_size(dplr_lr_plan p, int32_t which);
+
+/* Instrumentation (not part of the method).  When enabled, compute records a
+ * HIP event pair on the plan's stream around each of its kernels.
+ * profile_read synchronises the plan's stream, adds the elapsed times of all
+ * recorded pairs to per-stage totals and writes, for stage i < max, the
+ * summed milliseconds ms[i] and the number of launches calls[i]; *n (may be
+ * NULL) receives the number of stages; reset != 0 clears the totals after
+ * reading.  profile_stage_name(i) names stage i ("" when out of range). */
+dplr_lr_status dplr_lr_profile_enable(dplr_lr_plan p, int32_t enable);
+dplr_lr_status dplr_lr_profile_read(dplr_lr_plan p, double* ms, int64_t* calls, int32_t max, int32_t* n,
+                                    int32_t reset);
+const char* dplr_lr_profile_stage_name(int32_t i);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPLR_LR_H */

@@ -1,0 +1,631 @@
+// Host runtime and C ABI of the DPLR long-range PPPM step (see include/dplr_lr.h).
+#include "../../include/dplr_lr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pppm_kernels.hpp"
+
+using namespace dplr;
+
+namespace {
+
+thread_local std::string g_global_error;
+
+#ifndef DPLR_SPREAD_MIN_THREADS
+#define DPLR_SPREAD_MIN_THREADS 256
+#endif
+#ifndef DPLR_GATHER_MIN_THREADS
+#define DPLR_GATHER_MIN_THREADS 256
+#endif
+
+constexpr int kMinMesh = 16;
+constexpr int kMaxMesh = 512;
+constexpr int kMaxOrder = 8;
+constexpr int kMinOrder = 2;
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int round_threads(long elems) {
+  long t = (elems + kEPT - 1) / kEPT;
+  t = ((t + 63) / 64) * 64;
+  if (t < 64) t = 64;
+  if (t > 1024) t = 1024;
+  return (int)t;
+}
+
+dplr_lr_status validate(const dplr_lr_config* c, std::string& msg) {
+  if (!c) { msg = "config is NULL"; return DPLR_LR_E_INVALID; }
+  for (int a = 0; a < 3; ++a) {
+    if (c->mesh[a] <= 0) { msg = "mesh sizes must be positive"; return DPLR_LR_E_INVALID; }
+    if (!is_pow2(c->mesh[a]) || c->mesh[a] < kMinMesh || c->mesh[a] > kMaxMesh) {
+      msg = "mesh sizes must be powers of two in [16, 512]";
+      return DPLR_LR_E_UNSUPPORTED;
+    }
+  }
+  if (c->order < kMinOrder || c->order > kMaxOrder) {
+    msg = "order must be in [2, 8]";
+    return c->order <= 0 ? DPLR_LR_E_INVALID : DPLR_LR_E_UNSUPPORTED;
+  }
+  if (!(c->beta > 0.0) || !std::isfinite(c->beta)) { msg = "beta must be positive and finite"; return DPLR_LR_E_INVALID; }
+  if (!std::isfinite(c->coulomb_k)) { msg = "coulomb_k must be finite"; return DPLR_LR_E_INVALID; }
+  if (c->precision != DPLR_LR_FP32 && c->precision != DPLR_LR_FP64) { msg = "precision must be FP32 or FP64"; return DPLR_LR_E_INVALID; }
+  if (c->alias_range < 0 || c->alias_range > 4) { msg = "alias_range must be in [0, 4]"; return DPLR_LR_E_INVALID; }
+  if (c->capacity < 0 || c->capacity > 0x7fffffffLL) { msg = "capacity must be in [0, 2^31-1]"; return DPLR_LR_E_INVALID; }
+  if (c->flags & ~(uint32_t)(DPLR_LR_ACCUMULATE | DPLR_LR_NO_VIRIAL)) { msg = "unknown flag bits"; return DPLR_LR_E_INVALID; }
+  return DPLR_LR_OK;
+}
+
+}  // namespace
+
+struct dplr_lr_plan_s {
+  dplr_lr_config cfg{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool fp64 = false;
+  size_t tsize = 4;
+  Geo geo{};
+  double box[3] = {0, 0, 0};
+  bool has_box = false;
+  size_t lds_budget = 65536;
+  size_t lds_spread = 0, lds_ffty = 0, lds_z = 0, lds_gather = 0;
+  int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_gather = 256;
+  // device workspace
+  int* bin_count = nullptr;
+  int* bin_start = nullptr;
+  int* bin_cursor = nullptr;
+  int* bin_hist = nullptr;    // [max chunks][nbins]
+  bool block_hist = false;    // bins fit in LDS: sort without global atomics
+  int max_chunks = 256;
+  void* sorted = nullptr;
+  int* perm = nullptr;
+  int* sidx = nullptr;
+  void* spec = nullptr;
+  void* fspec = nullptr;
+  double* G = nullptr;
+  double* partials = nullptr;
+  void* twiddle = nullptr;
+  int64_t ws_bytes = 0;
+  std::vector<void*> allocs;
+  std::string err;
+  // instrumentation: HIP event pairs around each kernel of compute
+  bool prof = false;
+  struct ProfRec { int stage; hipEvent_t a, b; };
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  double prof_ms[16] = {0};
+  int64_t prof_calls[16] = {0};
+};
+
+namespace {
+
+const char* const kStageNames[] = {"bin_count", "bin_scan", "bin_scatter", "spread_fftx", "ffty_fwd",
+                                   "fftz_poisson", "ffty_inv", "ifftx_gather", "reduce"};
+constexpr int kNumStages = 9;
+
+hipEvent_t prof_event(dplr_lr_plan p) {
+  if (!p->prof_pool.empty()) {
+    hipEvent_t e = p->prof_pool.back();
+    p->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Records an event pair around one kernel launch when instrumentation is on.
+struct ProfScope {
+  dplr_lr_plan p;
+  int stage;
+  hipEvent_t a = nullptr;
+  ProfScope(dplr_lr_plan p_, int s) : p(p_), stage(s) {
+    if (p->prof) {
+      a = prof_event(p);
+      (void)hipEventRecord(a, p->stream);
+    }
+  }
+  ~ProfScope() {
+    if (p->prof && a) {
+      hipEvent_t b = prof_event(p);
+      (void)hipEventRecord(b, p->stream);
+      p->prof_pending.push_back({stage, a, b});
+    }
+  }
+};
+
+dplr_lr_status fail(dplr_lr_plan p, dplr_lr_status st, const std::string& m) {
+  if (p) p->err = m; else g_global_error = m;
+  return st;
+}
+
+dplr_lr_status hip_fail(dplr_lr_plan p, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(p, e == hipErrorOutOfMemory ? DPLR_LR_E_NOMEM : DPLR_LR_E_DEVICE, m);
+}
+
+template <typename T>
+size_t cpx_bytes() { return sizeof(cpx<T>); }
+
+// Choose tilings that fit the LDS budget.
+bool choose_geometry(dplr_lr_plan p) {
+  Geo& g = p->geo;
+  const int Kx = p->cfg.mesh[0], Ky = p->cfg.mesh[1], Kz = p->cfg.mesh[2];
+  const int P = p->cfg.order;
+  const size_t ts = p->tsize, cs = 2 * ts;
+  g.K[0] = Kx; g.K[1] = Ky; g.K[2] = Kz;
+  g.Kh = Kx / 2 + 1;
+  g.NQ = Ky / 4;
+  g.nbins = Kz * g.NQ;
+  g.twN = std::max(Kx, std::max(Ky, Kz));
+  const size_t twb = g.twN * cs;
+  const size_t budget = p->lds_budget - 1024;  // static LDS (ranges, reductions)
+
+  const int cand[][2] = {{16, 4}, {8, 4}, {16, 2}, {8, 2}, {4, 4}, {4, 2}, {8, 1}, {4, 1}};
+  g.scy = 0;
+  for (auto& c : cand) {
+    const int cy = c[0], cz = c[1];
+    if (cy > Ky || cz > Kz || (cy * cz) % 2) continue;
+    // 64-bit fixed-point accumulators, converted in place to complex pairs
+    const size_t b = (size_t)cy * cz * Kx * sizeof(long long) + twb;
+    const long long elems = (long long)cy * cz * Kx;
+    if (b <= budget && elems <= 16LL * 1024) {
+      g.scy = cy; g.scz = cz; p->lds_spread = b;
+      break;
+    }
+  }
+  if (!g.scy) return false;
+  g.spy = Ky / g.scy; g.spz = Kz / g.scz;
+  // the in-place fixed-point conversion holds at most 16 values per thread
+  p->thr_spread = std::max(DPLR_SPREAD_MIN_THREADS, round_threads((long)g.scy * g.scz / 2 * Kx));
+  while ((long)p->thr_spread * 16 < (long)g.scy * g.scz * Kx && p->thr_spread < 1024) p->thr_spread += 64;
+
+  const int gcand[][2] = {{8, 4}, {4, 4}, {8, 2}, {4, 2}, {4, 1}};
+  g.gcy = 0;
+  for (auto& c : gcand) {
+    const int cy = c[0], cz = c[1];
+    if (cy > Ky || cz > Kz) continue;
+    const int nrows = (cy + P - 1) * (cz + P - 1);
+    const int nrc = (nrows + 1) / 2;
+    const size_t b = (size_t)nrc * Kx * cs + twb;
+    if (b <= budget && (long)nrc * Kx <= (long)kEPT * 1024) {
+      g.gcy = cy; g.gcz = cz; p->lds_gather = b;
+      p->thr_gather = std::max(DPLR_GATHER_MIN_THREADS, round_threads((long)nrc * Kx));
+      break;
+    }
+  }
+  if (!g.gcy) return false;
+  g.gpy = Ky / g.gcy; g.gpz = Kz / g.gcz;
+
+  // y pass: blocks of zb contiguous rows, about 4096 complex elements
+  g.zb = std::max(1, std::min(Kz, 4096 / Ky));
+  while (g.zb > 1 && (size_t)g.zb * Ky * cs + twb > budget) g.zb /= 2;
+  p->lds_ffty = (size_t)g.zb * Ky * cs + twb;
+  p->thr_ffty = round_threads((long)g.zb * Ky);
+
+  // z pass: yb columns x Kz x 3 fields
+  g.yb = std::min(16, Ky);
+  while (g.yb > 1 && ((size_t)3 * g.yb * Kz * cs + twb > budget || (long)3 * g.yb * Kz > (long)kEPT * 1024)) g.yb /= 2;
+  p->lds_z = (size_t)3 * g.yb * Kz * cs + twb;
+  p->thr_z = round_threads((long)3 * g.yb * Kz);
+  g.nzblk = g.Kh * (Ky / g.yb);
+  return true;
+}
+
+template <typename T>
+void fill_twiddles(std::vector<unsigned char>& out, int N) {
+  out.resize(sizeof(cpx<T>) * N);
+  cpx<T>* w = reinterpret_cast<cpx<T>*>(out.data());
+  for (int k = 0; k < N; ++k) {
+    const double th = -2.0 * M_PI * (double)k / (double)N;
+    w[k].x = (T)std::cos(th);
+    w[k].y = (T)std::sin(th);
+  }
+}
+
+dplr_lr_status alloc(dplr_lr_plan p, void** ptr, size_t bytes, const char* what) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) return hip_fail(p, e, what);
+  p->allocs.push_back(*ptr);
+  p->ws_bytes += (int64_t)bytes;
+  return DPLR_LR_OK;
+}
+
+void free_all(dplr_lr_plan p) {
+  for (void* a : p->allocs) (void)hipFree(a);
+  p->allocs.clear();
+}
+
+template <typename T>
+void set_lds_attrs(dplr_lr_plan p) {
+  // kernels whose dynamic LDS can exceed the 64 KiB default
+  auto attr = [&](const void* f, size_t b) {
+    if (b > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+  };
+  switch (p->cfg.order) {
+#define DPLR_ATTR(PP)                                                        \
+  case PP:                                                                   \
+    attr((const void*)k_spread_fftx<T, PP>, p->lds_spread);                  \
+    attr((const void*)k_ifftx_gather<T, PP>, p->lds_gather);                 \
+    break;
+    DPLR_ATTR(2) DPLR_ATTR(3) DPLR_ATTR(4) DPLR_ATTR(5) DPLR_ATTR(6) DPLR_ATTR(7) DPLR_ATTR(8)
+#undef DPLR_ATTR
+  }
+  switch (p->cfg.order) {
+#define DPLR_ATTR2(PP)                                                                   \
+  case PP:                                                                               \
+    attr((const void*)k_bin_hist<T, PP>, sizeof(int) * (size_t)p->geo.nbins);           \
+    attr((const void*)k_bin_place<T, PP>, sizeof(int) * (size_t)p->geo.nbins);          \
+    break;
+    DPLR_ATTR2(2) DPLR_ATTR2(3) DPLR_ATTR2(4) DPLR_ATTR2(5) DPLR_ATTR2(6) DPLR_ATTR2(7) DPLR_ATTR2(8)
+#undef DPLR_ATTR2
+  }
+  attr((const void*)k_ffty<T, false>, p->lds_ffty);
+  attr((const void*)k_ffty<T, true>, p->lds_ffty);
+  attr((const void*)k_fftz_poisson<T>, p->lds_z);
+}
+
+template <typename T, int P>
+dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, const void* ion_q, int64_t n_wc,
+                           const void* wc_pos, const void* wc_q, void* ion_force, void* wc_force, double* energy,
+                           double* virial) {
+  const Geo& g = p->geo;
+  hipStream_t s = p->stream;
+  const int64_t n = n_ion + n_wc;
+  const double ih[3] = {g.K[0] / p->box[0], g.K[1] / p->box[1], g.K[2] / p->box[2]};
+  const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(p->twiddle);
+  T4<T>* sorted = reinterpret_cast<T4<T>*>(p->sorted);
+  cpx<T>* spec = reinterpret_cast<cpx<T>*>(p->spec);
+  cpx<T>* fspec = reinterpret_cast<cpx<T>*>(p->fspec);
+  const T* ip = (const T*)ion_pos;
+  const T* wp = (const T*)wc_pos;
+
+  if (p->block_hist) {
+    // chunk size: multiple of 1024, at most max_chunks chunks
+    int64_t chunk = std::max<int64_t>(1024, ((n + p->max_chunks - 1) / p->max_chunks + 1023) / 1024 * 1024);
+    const int nblk = (int)((n + chunk - 1) / chunk);
+    const size_t lds = sizeof(int) * g.nbins;
+    if (n > 0) {
+      ProfScope ps(p, 0);
+      hipLaunchKernelGGL((k_bin_hist<T, P>), dim3(nblk), dim3(1024), lds, s, ip, wp, n_ion, n, ih[0], ih[1], ih[2],
+                         p->bin_hist, (int)chunk, g);
+    }
+    {
+      ProfScope ps(p, 1);
+      if (n > 0) {
+        hipLaunchKernelGGL(k_bin_colscan, dim3((g.nbins + 63) / 64), dim3(64), 0, s, p->bin_hist, p->bin_count,
+                           nblk, g.nbins);
+      } else {
+        hipLaunchKernelGGL(k_fill_int, dim3((g.nbins + 255) / 256), dim3(256), 0, s, p->bin_count, g.nbins, 0);
+      }
+      hipLaunchKernelGGL(k_bin_totscan, dim3(1), dim3(1024), 0, s, p->bin_count, p->bin_start, g.nbins);
+    }
+    if (n > 0) {
+      ProfScope ps(p, 2);
+      hipLaunchKernelGGL((k_bin_place<T, P>), dim3(nblk), dim3(1024), lds, s, ip, wp, (const T*)ion_q,
+                         (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], p->bin_hist, p->bin_start, sorted, p->sidx,
+                         p->perm, (int)chunk, g);
+    }
+  } else {
+    if (n > 0) {
+      const int nb = (int)((n + 255) / 256);
+      ProfScope ps(p, 0);
+      hipLaunchKernelGGL((k_bin_count<T, P>), dim3(nb), dim3(256), 0, s, ip, wp, n_ion, n, ih[0], ih[1], ih[2],
+                         p->bin_count, g);
+    }
+    {
+      ProfScope ps(p, 1);
+      hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, p->bin_count, p->bin_start, p->bin_cursor,
+                         g.nbins);
+    }
+    if (n > 0) {
+      const int nb = (int)((n + 255) / 256);
+      ProfScope ps(p, 2);
+      hipLaunchKernelGGL((k_bin_scatter<T, P>), dim3(nb), dim3(256), 0, s, ip, wp, (const T*)ion_q, (const T*)wc_q,
+                         n_ion, n, ih[0], ih[1], ih[2], p->bin_cursor, sorted, p->sidx, p->perm, g);
+    }
+  }
+  {
+    ProfScope ps(p, 3);
+    hipLaunchKernelGGL((k_spread_fftx<T, P>), dim3(g.spy * g.spz), dim3(p->thr_spread), p->lds_spread, s, sorted,
+                       p->sidx, p->bin_start, spec, tw, g);
+  }
+  {
+    ProfScope ps(p, 4);
+    hipLaunchKernelGGL((k_ffty<T, false>), dim3(g.Kh * (g.K[2] / g.zb)), dim3(p->thr_ffty), p->lds_ffty, s, spec, tw, g);
+  }
+  PoissonConsts pc;
+  for (int a = 0; a < 3; ++a) pc.two_pi_over_L[a] = 2.0 * M_PI / p->box[a];
+  pc.inv_4beta2 = 1.0 / (4.0 * p->cfg.beta * p->cfg.beta);
+  {
+    ProfScope ps(p, 5);
+    hipLaunchKernelGGL((k_fftz_poisson<T>), dim3(g.nzblk), dim3(p->thr_z), p->lds_z, s, spec, fspec, p->G,
+                       p->partials, tw, g, pc);
+  }
+  {
+    ProfScope ps(p, 6);
+    hipLaunchKernelGGL((k_ffty<T, true>), dim3(3 * g.Kh * (g.K[2] / g.zb)), dim3(p->thr_ffty), p->lds_ffty, s,
+                       fspec, tw, g);
+  }
+  const double V = p->box[0] * p->box[1] * p->box[2];
+  if (n > 0) {
+    ProfScope ps(p, 7);
+    hipLaunchKernelGGL((k_ifftx_gather<T, P>), dim3(g.gpy * g.gpz), dim3(p->thr_gather), p->lds_gather, s, fspec,
+                       sorted, p->sidx, p->perm, p->bin_start, (T*)ion_force, (T*)wc_force, n_ion, (T)(p->cfg.coulomb_k / V),
+                       (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0, tw, g);
+  }
+  const bool want_virial = !(p->cfg.flags & DPLR_LR_NO_VIRIAL) && virial;
+  {
+    ProfScope ps(p, 8);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, p->partials, g.nzblk, p->cfg.coulomb_k / (2.0 * V),
+                       energy, want_virial ? virial : (double*)nullptr);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
+  return DPLR_LR_OK;
+}
+
+template <typename T>
+dplr_lr_status dispatch_order(dplr_lr_plan p, int64_t n_ion, const void* a, const void* b, int64_t n_wc,
+                              const void* c, const void* d, void* e, void* f, double* en, double* vir) {
+  switch (p->cfg.order) {
+    case 2: return launch_step<T, 2>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+    case 3: return launch_step<T, 3>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+    case 4: return launch_step<T, 4>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+    case 5: return launch_step<T, 5>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+    case 6: return launch_step<T, 6>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+    case 7: return launch_step<T, 7>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+    case 8: return launch_step<T, 8>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+  }
+  return fail(p, DPLR_LR_E_UNSUPPORTED, "order");
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t dplr_lr_abi_version(void) { return DPLR_LR_ABI_VERSION; }
+
+void dplr_lr_config_default(dplr_lr_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->mesh[0] = cfg->mesh[1] = cfg->mesh[2] = 32;
+  cfg->order = 5;
+  cfg->beta = 0.4;
+  cfg->coulomb_k = 14.399645;
+  cfg->precision = DPLR_LR_FP32;
+  cfg->alias_range = 2;
+  cfg->capacity = 0;
+  cfg->flags = 0;
+}
+
+dplr_lr_status dplr_lr_config_validate(const dplr_lr_config* cfg, char* msg, int64_t msg_len) {
+  std::string m;
+  dplr_lr_status st = validate(cfg, m);
+  if (st != DPLR_LR_OK) g_global_error = m;
+  if (msg && msg_len > 0) {
+    std::snprintf(msg, (size_t)msg_len, "%s", m.c_str());
+  }
+  return st;
+}
+
+dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, dplr_lr_plan* out) {
+  if (!out) return fail(nullptr, DPLR_LR_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::string m;
+  dplr_lr_status st = validate(cfg, m);
+  if (st != DPLR_LR_OK) return fail(nullptr, st, m);
+
+  dplr_lr_plan p = new (std::nothrow) dplr_lr_plan_s();
+  if (!p) return fail(nullptr, DPLR_LR_E_NOMEM, "host allocation");
+  p->cfg = *cfg;
+  p->stream = (hipStream_t)hip_stream;
+  p->fp64 = cfg->precision == DPLR_LR_FP64;
+  p->tsize = p->fp64 ? sizeof(double) : sizeof(float);
+
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { delete p; return hip_fail(nullptr, e, "hipGetDevice"); }
+  int lds = 0;
+  e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+  if (e != hipSuccess) { delete p; return hip_fail(nullptr, e, "hipDeviceGetAttribute"); }
+  p->lds_budget = (size_t)std::min(lds, 160 * 1024);
+  if (!choose_geometry(p)) {
+    delete p;
+    return fail(nullptr, DPLR_LR_E_UNSUPPORTED, "no tiling fits the device's LDS for this mesh/order/precision");
+  }
+  const Geo& g = p->geo;
+  const size_t ts = p->tsize, cs = 2 * ts;
+  const size_t cap = (size_t)std::max<int64_t>(cfg->capacity, 1);
+  const size_t nspec = (size_t)g.Kh * g.K[1] * g.K[2];
+  const size_t ng = (size_t)g.Kh * (g.K[1] / 2 + 1) * (g.K[2] / 2 + 1);
+  dplr_lr_status s2 = DPLR_LR_OK;
+#define DPLR_ALLOC(ptr, bytes, what)                                  \
+  if (s2 == DPLR_LR_OK) {                                             \
+    void* tmp__ = nullptr;                                            \
+    s2 = alloc(p, &tmp__, (bytes), what);                             \
+    ptr = reinterpret_cast<decltype(ptr)>(tmp__);                     \
+  }
+  DPLR_ALLOC(p->bin_count, sizeof(int) * (g.nbins + 1), "bin_count");
+  DPLR_ALLOC(p->bin_start, sizeof(int) * (g.nbins + 1), "bin_start");
+  DPLR_ALLOC(p->bin_cursor, sizeof(int) * (g.nbins + 1), "bin_cursor");
+  p->block_hist = (size_t)g.nbins * sizeof(int) <= std::min<size_t>(p->lds_budget, 65536);
+  if (p->block_hist) DPLR_ALLOC(p->bin_hist, sizeof(int) * (size_t)p->max_chunks * g.nbins, "bin histograms");
+  DPLR_ALLOC(p->sorted, 4 * ts * cap, "sorted");
+  DPLR_ALLOC(p->perm, sizeof(int) * cap, "perm");
+  DPLR_ALLOC(p->sidx, sizeof(int) * cap, "stencil starts");
+  DPLR_ALLOC(p->spec, cs * nspec, "spectrum");
+  DPLR_ALLOC(p->fspec, 3 * cs * nspec, "field spectra");
+  DPLR_ALLOC(p->G, sizeof(double) * ng, "influence");
+  DPLR_ALLOC(p->partials, sizeof(double) * 8 * g.nzblk, "partials");
+  DPLR_ALLOC(p->twiddle, cs * g.twN, "twiddles");
+#undef DPLR_ALLOC
+  if (s2 != DPLR_LR_OK) {
+    g_global_error = p->err;
+    free_all(p);
+    delete p;
+    return s2;
+  }
+  std::vector<unsigned char> tw;
+  if (p->fp64) fill_twiddles<double>(tw, g.twN); else fill_twiddles<float>(tw, g.twN);
+  e = hipMemcpy(p->twiddle, tw.data(), tw.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(p->bin_count, 0, sizeof(int) * (g.nbins + 1));
+  if (e == hipSuccess) e = hipMemset(p->G, 0, sizeof(double) * ng);
+  if (e != hipSuccess) {
+    dplr_lr_status r = hip_fail(nullptr, e, "workspace init");
+    free_all(p);
+    delete p;
+    return r;
+  }
+  if (p->fp64) set_lds_attrs<double>(p); else set_lds_attrs<float>(p);
+  *out = p;
+  return DPLR_LR_OK;
+}
+
+dplr_lr_status dplr_lr_set_stream(dplr_lr_plan p, void* hip_stream) {
+  if (!p) return fail(nullptr, DPLR_LR_E_INVALID, "plan is NULL");
+  p->stream = (hipStream_t)hip_stream;
+  return DPLR_LR_OK;
+}
+
+dplr_lr_status dplr_lr_set_box(dplr_lr_plan p, const double box_len[3]) {
+  if (!p) return fail(nullptr, DPLR_LR_E_INVALID, "plan is NULL");
+  if (!box_len) return fail(p, DPLR_LR_E_INVALID, "box_len is NULL");
+  for (int a = 0; a < 3; ++a) {
+    if (!(box_len[a] > 0.0) || !std::isfinite(box_len[a])) return fail(p, DPLR_LR_E_INVALID, "box lengths must be positive and finite");
+  }
+  for (int a = 0; a < 3; ++a) p->box[a] = box_len[a];
+  const Geo& g = p->geo;
+  const int64_t ng = (int64_t)g.Kh * (g.K[1] / 2 + 1) * (g.K[2] / 2 + 1);
+  hipLaunchKernelGGL(k_influence, dim3((unsigned)((ng + 127) / 128)), dim3(128), 0, p->stream, p->G, g, p->box[0],
+                     p->box[1], p->box[2], p->cfg.beta, p->cfg.order, p->cfg.alias_range);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(p, e, "influence launch");
+  p->has_box = true;
+  return DPLR_LR_OK;
+}
+
+dplr_lr_status dplr_lr_compute_energy_forces_virial(dplr_lr_plan p, int64_t n_ion, const void* ion_pos,
+                                                    const void* ion_q, int64_t n_wc, const void* wc_pos,
+                                                    const void* wc_q, void* ion_force, void* wc_force,
+                                                    double* energy, double* virial6) {
+  if (!p) return fail(nullptr, DPLR_LR_E_INVALID, "plan is NULL");
+  if (n_ion < 0 || n_wc < 0) return fail(p, DPLR_LR_E_INVALID, "negative particle count");
+  if (n_ion > 0 && (!ion_pos || !ion_q || !ion_force)) return fail(p, DPLR_LR_E_INVALID, "ion pointer is NULL");
+  if (n_wc > 0 && (!wc_pos || !wc_q || !wc_force)) return fail(p, DPLR_LR_E_INVALID, "wc pointer is NULL");
+  if (!energy) return fail(p, DPLR_LR_E_INVALID, "energy is NULL");
+  if (!virial6 && !(p->cfg.flags & DPLR_LR_NO_VIRIAL)) return fail(p, DPLR_LR_E_INVALID, "virial6 is NULL");
+  if (!p->has_box) return fail(p, DPLR_LR_E_NO_BOX, "set_box has not been called");
+  if (n_ion + n_wc > p->cfg.capacity) return fail(p, DPLR_LR_E_CAPACITY, "n_ion + n_wc exceeds the plan capacity");
+  if (p->fp64) return dispatch_order<double>(p, n_ion, ion_pos, ion_q, n_wc, wc_pos, wc_q, ion_force, wc_force, energy, virial6);
+  return dispatch_order<float>(p, n_ion, ion_pos, ion_q, n_wc, wc_pos, wc_q, ion_force, wc_force, energy, virial6);
+}
+
+dplr_lr_status dplr_lr_scale_grad(dplr_lr_plan p, const double* grad_energy, int64_t n_ion, const void* ion_force,
+                                  void* ion_grad, int64_t n_wc, const void* wc_force, void* wc_grad) {
+  if (!p) return fail(nullptr, DPLR_LR_E_INVALID, "plan is NULL");
+  if (!grad_energy) return fail(p, DPLR_LR_E_INVALID, "grad_energy is NULL");
+  if (n_ion < 0 || n_wc < 0) return fail(p, DPLR_LR_E_INVALID, "negative particle count");
+  if (n_ion > 0 && (!ion_force || !ion_grad)) return fail(p, DPLR_LR_E_INVALID, "ion pointer is NULL");
+  if (n_wc > 0 && (!wc_force || !wc_grad)) return fail(p, DPLR_LR_E_INVALID, "wc pointer is NULL");
+  const int64_t m[2] = {3 * n_ion, 3 * n_wc};
+  const void* src[2] = {ion_force, wc_force};
+  void* dst[2] = {ion_grad, wc_grad};
+  for (int i = 0; i < 2; ++i) {
+    if (m[i] == 0) continue;
+    const unsigned nb = (unsigned)((m[i] + 255) / 256);
+    if (p->fp64)
+      hipLaunchKernelGGL(k_scale_grad<double>, dim3(nb), dim3(256), 0, p->stream, grad_energy, (const double*)src[i], (double*)dst[i], m[i]);
+    else
+      hipLaunchKernelGGL(k_scale_grad<float>, dim3(nb), dim3(256), 0, p->stream, grad_energy, (const float*)src[i], (float*)dst[i], m[i]);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(p, e, "scale_grad launch");
+  return DPLR_LR_OK;
+}
+
+dplr_lr_status dplr_lr_plan_destroy(dplr_lr_plan p) {
+  if (!p) return DPLR_LR_OK;
+  (void)hipStreamSynchronize(p->stream);
+  for (auto& r : p->prof_pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  for (auto e : p->prof_pool) (void)hipEventDestroy(e);
+  free_all(p);
+  delete p;
+  return DPLR_LR_OK;
+}
+
+dplr_lr_status dplr_lr_profile_enable(dplr_lr_plan p, int32_t enable) {
+  if (!p) return fail(nullptr, DPLR_LR_E_INVALID, "plan is NULL");
+  p->prof = enable != 0;
+  return DPLR_LR_OK;
+}
+
+dplr_lr_status dplr_lr_profile_read(dplr_lr_plan p, double* ms, int64_t* calls, int32_t max, int32_t* n,
+                                    int32_t reset) {
+  if (!p) return fail(nullptr, DPLR_LR_E_INVALID, "plan is NULL");
+  if (max < 0 || (max > 0 && (!ms || !calls))) return fail(p, DPLR_LR_E_INVALID, "bad output arrays");
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(p, e, "profile sync");
+  for (auto& r : p->prof_pending) {
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e == hipSuccess) {
+      p->prof_ms[r.stage] += t;
+      p->prof_calls[r.stage] += 1;
+    }
+    p->prof_pool.push_back(r.a);
+    p->prof_pool.push_back(r.b);
+  }
+  p->prof_pending.clear();
+  for (int i = 0; i < kNumStages && i < max; ++i) {
+    ms[i] = p->prof_ms[i];
+    calls[i] = p->prof_calls[i];
+  }
+  if (n) *n = kNumStages;
+  if (reset) {
+    for (int i = 0; i < 16; ++i) { p->prof_ms[i] = 0; p->prof_calls[i] = 0; }
+  }
+  return DPLR_LR_OK;
+}
+
+const char* dplr_lr_profile_stage_name(int32_t i) {
+  return (i >= 0 && i < kNumStages) ? kStageNames[i] : "";
+}
+
+const char* dplr_lr_last_error(dplr_lr_plan p) {
+  return p ? p->err.c_str() : g_global_error.c_str();
+}
+
+int64_t dplr_lr_workspace_bytes(dplr_lr_plan p) { return p ? p->ws_bytes : 0; }
+
+int64_t dplr_lr_debug_size(dplr_lr_plan p, int32_t which) {
+  if (!p) return -1;
+  const Geo& g = p->geo;
+  const size_t cs = 2 * p->tsize;
+  const size_t nspec = (size_t)g.Kh * g.K[1] * g.K[2];
+  switch (which) {
+    case DPLR_LR_BUF_SPECTRUM: return (int64_t)(cs * nspec);
+    case DPLR_LR_BUF_INFLUENCE: return (int64_t)(sizeof(double) * g.Kh * (g.K[1] / 2 + 1) * (g.K[2] / 2 + 1));
+    case DPLR_LR_BUF_FIELD_SPECTRA: return (int64_t)(3 * cs * nspec);
+  }
+  return -1;
+}
+
+dplr_lr_status dplr_lr_debug_copy(dplr_lr_plan p, int32_t which, void* dst, int64_t bytes) {
+  if (!p) return fail(nullptr, DPLR_LR_E_INVALID, "plan is NULL");
+  const int64_t size = dplr_lr_debug_size(p, which);
+  if (size < 0) return fail(p, DPLR_LR_E_INVALID, "unknown buffer");
+  if (!dst || bytes < 0 || bytes > size) return fail(p, DPLR_LR_E_INVALID, "bad destination or size");
+  const void* src = which == DPLR_LR_BUF_SPECTRUM ? p->spec : which == DPLR_LR_BUF_INFLUENCE ? (const void*)p->G : p->fspec;
+  hipError_t e = hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, p->stream);
+  if (e != hipSuccess) return hip_fail(p, e, "debug copy");
+  return DPLR_LR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,744 @@
+// PPPM-ik kernels for gfx950.
+//
+// Data layout in HBM (FP32 plan; FP64 doubles every element):
+//   sorted   [n] T4 (d_x, d_y, d_z, q): fractional B-spline offsets and charge,
+//            ordered by bin; sidx [n] int: stencil starts s_x | s_y<<10 | s_z<<20;
+//            perm [n] int: original index (ions 0..n_ion-1, then WCs).
+//   bins     one per (stencil-start plane s_z, stencil-start row quad s_y/4);
+//            bin_start [nbins+1].
+//   spec     half spectrum [Kx/2+1][Kz][Ky] complex (y fastest).
+//   fspec    three field spectra [3][Kx/2+1][Kz][Ky] complex.
+//   G        FP64 influence table [Kx/2+1][Ky/2+1][Kz/2+1] (G is even in
+//            every wave-vector component).
+#pragma once
+
+#include "device_common.hpp"
+
+namespace dplr {
+
+template <typename T>
+struct alignas(4 * sizeof(T)) T4 {
+  T x, y, z, w;
+};
+
+// Mesh/tiling geometry shared by all kernels of a plan (passed by value).
+struct Geo {
+  int K[3];      // Kx, Ky, Kz
+  int Kh;        // Kx/2 + 1
+  int NQ;        // Ky / 4
+  int nbins;     // Kz * NQ
+  int scy, scz;  // spread pencil cross-section (y, z); the pencil spans all x
+  int spy, spz;  // spread pencil counts
+  int gcy, gcz;  // gather pencil cross-section
+  int gpy, gpz;  // gather pencil counts
+  int zb;        // rows per block of the y-transform pass
+  int yb;        // columns per block of the z-transform pass
+  int twN;       // twiddle table length (max K)
+  int nzblk;     // z-pass blocks
+};
+
+struct PoissonConsts {
+  double two_pi_over_L[3];
+  double inv_4beta2;
+};
+
+constexpr int kEPT = 16;  // FFT elements per thread bound
+
+__device__ __forceinline__ int wrapi(int v, int K) {
+  v %= K;
+  return v < 0 ? v + K : v;
+}
+
+// ----------------------------------------------------------------------------
+// Wrap + bin: counting sort by stencil-start plane and row quad
+// ----------------------------------------------------------------------------
+// The mesh coordinate u = r K / L, its wrap into [0, K), the stencil start s
+// and the fractional offset d are computed in FP64 for both precisions: an
+// FP32 u near K = 128 would carry a rounding of ~1e-5 cells, which water's
+// tightly bound charges turn into ~1e-5 relative force error.  The FP32 path
+// then stores d in [0, 1] (absolute rounding ~6e-8) next to the integer s.
+template <typename T, int P>
+__device__ __forceinline__ void particle_bin(const T* __restrict__ ion_pos, const T* __restrict__ wc_pos,
+                                             int64_t n_ion, int64_t i, const double invh[3], const Geo& g,
+                                             T d_out[3], int& spack, int& bin) {
+  const T* r = (i < n_ion) ? (ion_pos + 3 * i) : (wc_pos + 3 * (i - n_ion));
+  int s[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double K = (double)g.K[a];
+    double v = (double)r[a] * invh[a];
+    v = v - K * floor(v / K);
+    if (v >= K) v -= K;
+    if (!(v >= 0.0 && v < K)) v = 0.0;  // also maps NaN/Inf inputs to 0
+    const double av = v - 0.5 * P;
+    const double f = floor(av);
+    d_out[a] = (T)(av - f);
+    int sa = (int)f + 1;
+    if (sa < 0) sa += g.K[a];
+    if (sa >= g.K[a]) sa -= g.K[a];
+    s[a] = sa;
+  }
+  spack = s[0] | (s[1] << 10) | (s[2] << 20);
+  bin = s[2] * g.NQ + (s[1] >> 2);
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_bin_count(const T* __restrict__ ion_pos, const T* __restrict__ wc_pos,
+                                                   int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
+                                                   int* __restrict__ count, Geo g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double invh[3] = {ihx, ihy, ihz};
+  T d[3];
+  int sp, bin;
+  particle_bin<T, P>(ion_pos, wc_pos, n_ion, i, invh, g, d, sp, bin);
+  atomicAdd(count + bin, 1);
+}
+
+// Exclusive scan of the bin counts (one block); also clears the counts for
+// the next call and seeds the scatter cursors.
+__global__ void __launch_bounds__(1024) k_bin_scan(int* __restrict__ count, int* __restrict__ start,
+                                                   int* __restrict__ cursor, int nbins) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int chunk = (nbins + nt - 1) / nt;
+  const int b0 = min(nbins, t * chunk), b1 = min(nbins, b0 + chunk);
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += count[b];
+  part[t] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the per-thread sums
+  for (int off = 1; off < nt; off <<= 1) {
+    int v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int b = b0; b < b1; ++b) {
+    const int c = count[b];
+    start[b] = run;
+    cursor[b] = run;
+    count[b] = 0;
+    run += c;
+  }
+  if (t == nt - 1) start[nbins] = part[t];
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_bin_scatter(const T* __restrict__ ion_pos, const T* __restrict__ wc_pos,
+                                                     const T* __restrict__ ion_q, const T* __restrict__ wc_q,
+                                                     int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
+                                                     int* __restrict__ cursor, T4<T>* __restrict__ sorted,
+                                                     int* __restrict__ sidx, int* __restrict__ perm, Geo g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double invh[3] = {ihx, ihy, ihz};
+  T d[3];
+  int sp, bin;
+  particle_bin<T, P>(ion_pos, wc_pos, n_ion, i, invh, g, d, sp, bin);
+  const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
+  const int slot = atomicAdd(cursor + bin, 1);
+  sorted[slot] = T4<T>{d[0], d[1], d[2], q};
+  sidx[slot] = sp;
+  perm[slot] = (int)i;
+}
+
+// Counting sort without global atomics (used when the bins fit in LDS).
+// Particles are cut into chunks of `chunk` consecutive indices; chunk c's
+// histogram is built with LDS atomics and stored densely in hist[c][bin];
+// a per-bin scan over chunks turns it into the chunk's offset inside the bin,
+// a scan over bins gives bin_start, and the scatter places particle i of
+// chunk c at bin_start[bin] + hist[c][bin] + (its rank within the chunk).
+template <typename T, int P>
+__global__ void __launch_bounds__(1024) k_bin_hist(const T* __restrict__ ion_pos, const T* __restrict__ wc_pos,
+                                                   int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
+                                                   int* __restrict__ hist, int chunk, Geo g) {
+  extern __shared__ int lh[];
+  for (int b = threadIdx.x; b < g.nbins; b += blockDim.x) lh[b] = 0;
+  __syncthreads();
+  const double invh[3] = {ihx, ihy, ihz};
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = min(n, i0 + chunk);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    T d[3];
+    int sp, bin;
+    particle_bin<T, P>(ion_pos, wc_pos, n_ion, i, invh, g, d, sp, bin);
+    atomicAdd(lh + bin, 1);
+  }
+  __syncthreads();
+  int* out = hist + (size_t)blockIdx.x * g.nbins;
+  for (int b = threadIdx.x; b < g.nbins; b += blockDim.x) out[b] = lh[b];
+}
+
+__global__ void k_fill_int(int* __restrict__ a, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// Per bin: exclusive scan of the chunk counts (in place) and the bin total.
+__global__ void __launch_bounds__(64) k_bin_colscan(int* __restrict__ hist, int* __restrict__ total, int nblk,
+                                                    int nbins) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  int run = 0;
+  int k = 0;
+  for (; k + 8 <= nblk; k += 8) {
+    int c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = hist[(size_t)(k + u) * nbins + b];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      hist[(size_t)(k + u) * nbins + b] = run;
+      run += c[u];
+    }
+  }
+  for (; k < nblk; ++k) {
+    const int c = hist[(size_t)k * nbins + b];
+    hist[(size_t)k * nbins + b] = run;
+    run += c;
+  }
+  total[b] = run;
+}
+
+// Exclusive scan of the bin totals (one block of 1024 threads).
+__global__ void __launch_bounds__(1024) k_bin_totscan(const int* __restrict__ total, int* __restrict__ start,
+                                                      int nbins) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int chunk = (nbins + nt - 1) / nt;
+  const int b0 = min(nbins, t * chunk), b1 = min(nbins, b0 + chunk);
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += total[b];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {
+    int v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int b = b0; b < b1; ++b) {
+    start[b] = run;
+    run += total[b];
+  }
+  if (t == nt - 1) start[nbins] = part[t];
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(1024) k_bin_place(const T* __restrict__ ion_pos, const T* __restrict__ wc_pos,
+                                                    const T* __restrict__ ion_q, const T* __restrict__ wc_q,
+                                                    int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
+                                                    const int* __restrict__ hist, const int* __restrict__ start,
+                                                    T4<T>* __restrict__ sorted, int* __restrict__ sidx,
+                                                    int* __restrict__ perm, int chunk, Geo g) {
+  extern __shared__ int lc[];
+  for (int b = threadIdx.x; b < g.nbins; b += blockDim.x) lc[b] = 0;
+  __syncthreads();
+  const double invh[3] = {ihx, ihy, ihz};
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = min(n, i0 + chunk);
+  const int* off = hist + (size_t)blockIdx.x * g.nbins;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    T d[3];
+    int sp, bin;
+    particle_bin<T, P>(ion_pos, wc_pos, n_ion, i, invh, g, d, sp, bin);
+    const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
+    const int slot = start[bin] + off[bin] + atomicAdd(lc + bin, 1);
+    sorted[slot] = T4<T>{d[0], d[1], d[2], q};
+    sidx[slot] = sp;
+    perm[slot] = (int)i;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Visit ranges of a pencil: the sorted particles whose stencil-start plane lies
+// in [z_lo, z_lo + nplanes) (mod Kz) and whose stencil-start row quad lies in
+// [q_lo, q_lo + nq) (mod NQ), as at most 2 contiguous ranges per plane.
+// ----------------------------------------------------------------------------
+struct Ranges {
+  int n;
+  int lo[48];
+  int pre[49];  // prefix sums of lengths
+};
+
+__device__ __forceinline__ void build_ranges(Ranges& R, const int* __restrict__ bin_start, const Geo& g,
+                                             int z_lo, int nplanes, int q_lo, int nq) {
+  int n = 0, acc = 0;
+  for (int i = 0; i < nplanes; ++i) {
+    const int z = wrapi(z_lo + i, g.K[2]);
+    const int qa = wrapi(q_lo, g.NQ);
+    int parts[2][2];
+    int np = 0;
+    if (qa + nq <= g.NQ) {
+      parts[0][0] = qa; parts[0][1] = qa + nq; np = 1;
+    } else {
+      parts[0][0] = qa; parts[0][1] = g.NQ;
+      parts[1][0] = 0; parts[1][1] = qa + nq - g.NQ; np = 2;
+    }
+    for (int j = 0; j < np; ++j) {
+      const int b0 = z * g.NQ + parts[j][0], b1 = z * g.NQ + parts[j][1];
+      const int p0 = bin_start[b0], p1 = bin_start[b1];
+      if (p1 > p0) {
+        R.lo[n] = p0;
+        R.pre[n] = acc;
+        acc += p1 - p0;
+        ++n;
+      }
+    }
+  }
+  R.pre[n] = acc;
+  R.n = n;
+}
+
+__device__ __forceinline__ int range_index(const Ranges& R, int v) {
+  int r = 0;
+  while (r + 1 < R.n && R.pre[r + 1] <= v) ++r;
+  return R.lo[r] + (v - R.pre[r]);
+}
+
+// ----------------------------------------------------------------------------
+// Fixed-point scale of the charge accumulators: 2^32 for FP32 plans (the
+// FP32 products are then summed exactly; |mesh charge| < 2^31), 2^40 for FP64
+// plans (rounding 2^-41 per term; |mesh charge| < 2^23).
+// c * 2^B rounded to a signed 64-bit integer.
+template <typename T>
+__device__ __forceinline__ long long to_fixed(T c) {
+  if constexpr (sizeof(T) == 4) {
+    // split c * 2^32 into floor(c) (high word) and the fraction (low word);
+    // both conversions are exact for |c| < 2^31
+    const float fl = floorf(c);
+    const float fr = (c - fl) * 4294967296.0f;   // in [0, 2^32)
+    const unsigned lo = (fr >= 4294967040.0f) ? 4294967040u : (unsigned)fr;
+    return (long long)(((unsigned long long)(long long)(int)fl << 32) | (unsigned long long)lo);
+  } else {
+    return (long long)llrint(c * 1099511627776.0);  // 2^40
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T from_fixed(long long v) {
+  return (T)((double)v * (sizeof(T) == 4 ? 2.3283064365386963e-10 : 9.094947017729282e-13));
+}
+
+// ----------------------------------------------------------------------------
+// Charge spreading into an LDS pencil (owner computes its halo), then the
+// real-to-complex transform along x.
+//
+// One workgroup owns rows y in [y0, y0+scy), z in [z0, z0+scz), all x.  It
+// visits every particle whose stencil touches those rows (its own bins and
+// the p-1 planes / one row group below) and adds only the owned part of each
+// stencil, so every mesh value is complete inside one LDS tile and no
+// workgroup writes another's rows (no global atomics, no halo buffers).
+// Accumulation is in 64-bit fixed point with integer LDS atomics: on gfx950
+// these run ~15x faster than LDS float atomics, and integer sums do not
+// depend on the order of the additions, so the mesh is bitwise repeatable.
+// After the spread the tile is converted in place to complex rows packed in
+// pairs (even row = real part, odd row = imaginary part), so one complex FFT
+// transforms two real rows; the two half spectra are then separated with the
+// Hermitian symmetry of each.
+// ----------------------------------------------------------------------------
+template <typename T, int P>
+__global__ void __launch_bounds__(1024) k_spread_fftx(const T4<T>* __restrict__ sorted,
+                                                      const int* __restrict__ sidx,
+                                                      const int* __restrict__ bin_start,
+                                                      cpx<T>* __restrict__ spec,
+                                                      const cpx<T>* __restrict__ twg, Geo g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2];
+  const int nrows = g.scy * g.scz;
+  const int nrc = nrows >> 1;
+  long long* acc = reinterpret_cast<long long*>(smem);          // [nrows][Kx]
+  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem);               // [nrc][Kx] after conversion
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem + (size_t)nrows * Kx * sizeof(long long));
+  __shared__ Ranges R;
+
+  const int py = blockIdx.x % g.spy, pz = blockIdx.x / g.spy;
+  const int y0 = py * g.scy, z0 = pz * g.scz;
+
+  for (int e = threadIdx.x; e < nrows * Kx; e += blockDim.x) acc[e] = 0;
+  for (int e = threadIdx.x; e < g.twN; e += blockDim.x) tw[e] = twg[e];
+  if (threadIdx.x == 0) {
+    const int nplanes = min(g.scz + P - 1, Kz);
+    const int ylo = y0 - (P - 1);
+    const int q_lo = (ylo >= 0) ? (ylo >> 2) : -((3 - ylo) >> 2);
+    const int q_hi = (y0 + g.scy - 1) >> 2;
+    const int nq = min(q_hi - q_lo + 1, g.NQ);
+    build_ranges(R, bin_start, g, z0 - (P - 1), nplanes, q_lo, nq);
+  }
+  __syncthreads();
+
+  const int total = R.pre[R.n];
+  for (int v = threadIdx.x; v < total; v += blockDim.x) {
+    const int idx = range_index(R, v);
+    const T4<T> pt = sorted[idx];
+    const int sp = sidx[idx];
+    const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
+    T wx[P], wy[P], wz[P];
+    bspline_weights<T, P>(pt.x, wx);
+    bspline_weights<T, P>(pt.y, wy);
+    bspline_weights<T, P>(pt.z, wz);
+#pragma unroll
+    for (int tz = 0; tz < P; ++tz) {
+      int gz = sz + tz;
+      if (gz >= Kz) gz -= Kz;
+      const int lz = gz - z0;
+      if (lz < 0 || lz >= g.scz) continue;
+      const T qz = pt.w * wz[tz];
+#pragma unroll
+      for (int ty = 0; ty < P; ++ty) {
+        int gy = sy + ty;
+        if (gy >= Ky) gy -= Ky;
+        const int ly = gy - y0;
+        if (ly < 0 || ly >= g.scy) continue;
+        unsigned long long* rp = reinterpret_cast<unsigned long long*>(acc + (size_t)(lz * g.scy + ly) * Kx);
+        const T qyz = qz * wy[ty];
+#pragma unroll
+        for (int tx = 0; tx < P; ++tx) {
+          int gx = sx + tx;
+          if (gx >= Kx) gx -= Kx;
+          atomicAdd(rp + gx, (unsigned long long)to_fixed<T>(qyz * wx[tx]));
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // fixed point -> complex row pairs, in place: every thread first reads all
+  // of its values, the block synchronises, then it writes
+  {
+    constexpr int kMaxPer = 16;
+    long long v[kMaxPer];
+    const int per = (nrows * Kx + blockDim.x - 1) / blockDim.x;
+#pragma unroll
+    for (int c = 0; c < kMaxPer; ++c) {
+      const int e = threadIdx.x + c * blockDim.x;
+      if (c < per && e < nrows * Kx) v[c] = acc[e];
+    }
+    __syncthreads();
+    T* out = reinterpret_cast<T*>(tile);
+#pragma unroll
+    for (int c = 0; c < kMaxPer; ++c) {
+      const int e = threadIdx.x + c * blockDim.x;
+      if (c < per && e < nrows * Kx) {
+        const int row = e / Kx, x = e - row * Kx;
+        out[2 * ((row >> 1) * Kx + x) + (row & 1)] = from_fixed<T>(v[c]);
+      }
+    }
+    __syncthreads();
+  }
+
+  fft_rows<T, false, kEPT>(tile, nrc, Kx, Kx, 1, false, tw, g.twN);
+
+  const int Kh = g.Kh;
+  for (int e = threadIdx.x; e < nrows * Kh; e += blockDim.x) {
+    const int ly = e % g.scy;
+    const int rest = e / g.scy;
+    const int lz = rest % g.scz;
+    const int k = rest / g.scz;
+    const int row = lz * g.scy + ly;
+    const cpx<T>* zr = tile + (row >> 1) * Kx;
+    const cpx<T> z1 = zr[k];
+    const cpx<T> z2 = cconj(zr[(Kx - k) & (Kx - 1)]);
+    cpx<T> out;
+    if ((row & 1) == 0) {
+      out = cpx<T>{(T)0.5 * (z1.x + z2.x), (T)0.5 * (z1.y + z2.y)};
+    } else {
+      const cpx<T> d = csub(z1, z2);
+      out = cpx<T>{(T)0.5 * d.y, (T)-0.5 * d.x};
+    }
+    spec[((size_t)k * Kz + (z0 + lz)) * Ky + (y0 + ly)] = out;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Transforms along y of contiguous blocks of zb rows (forward on the charge
+// spectrum, inverse on the three field spectra).
+// Used forward on spec and inverse on the three field spectra.
+// ----------------------------------------------------------------------------
+template <typename T, bool INV>
+__global__ void __launch_bounds__(1024) k_ffty(cpx<T>* __restrict__ data, const cpx<T>* __restrict__ twg, Geo g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Ky = g.K[1], Kz = g.K[2];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);
+  cpx<T>* tw = buf + g.zb * Ky;
+  const int nzb = Kz / g.zb;
+  const int plane = blockIdx.x / nzb, zblk = blockIdx.x % nzb;
+  cpx<T>* base = data + ((size_t)plane * Kz + (size_t)zblk * g.zb) * Ky;
+  for (int e = threadIdx.x; e < g.zb * Ky; e += blockDim.x) buf[e] = base[e];
+  for (int e = threadIdx.x; e < g.twN; e += blockDim.x) tw[e] = twg[e];
+  __syncthreads();
+  fft_rows<T, INV, kEPT>(buf, g.zb, Ky, Ky, 1, false, tw, g.twN);
+  for (int e = threadIdx.x; e < g.zb * Ky; e += blockDim.x) base[e] = buf[e];
+}
+
+// ----------------------------------------------------------------------------
+// Forward transform along z of yb columns of
+// one kx plane, the influence-function multiply with ik-differentiation, the
+// FP64 energy and virial partial sums, and the three inverse z transforms.
+//
+//   E^_a(n) = -i k'_a G(n) Q^(n),  k' = k with the Nyquist component zeroed;
+//   e  = sum w G |Q^|^2,  w = 1 on the kx = 0 and kx = Kx/2 planes, else 2;
+//   v_ab = sum w G |Q^|^2 (delta_ab - 2 (1 + k^2/(4 beta^2)) k_a k_b / k^2)
+//   (off-diagonal products use k', since full-spectrum terms with a Nyquist
+//   component cancel in +-n pairs).
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict__ spec, cpx<T>* __restrict__ fspec,
+                                                       const double* __restrict__ G, double* __restrict__ partials,
+                                                       const cpx<T>* __restrict__ twg, Geo g, PoissonConsts pc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2], Kh = g.Kh;
+  const int yb = g.yb, w3 = 3 * yb;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);  // [Kz][3*yb]
+  cpx<T>* tw = buf + Kz * w3;
+  __shared__ double red[16][8];
+
+  const int nyb = Ky / yb;
+  const int kx = blockIdx.x / nyb, y0 = (blockIdx.x % nyb) * yb;
+  for (int e = threadIdx.x; e < Kz * yb; e += blockDim.x) {
+    const int yl = e % yb, z = e / yb;
+    buf[z * w3 + yl] = spec[((size_t)kx * Kz + z) * Ky + y0 + yl];
+  }
+  for (int e = threadIdx.x; e < g.twN; e += blockDim.x) tw[e] = twg[e];
+  __syncthreads();
+  fft_rows<T, false, kEPT>(buf, yb, Kz, 1, w3, true, tw, g.twN);
+
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  const int Kyh = Ky / 2 + 1, Kzh = Kz / 2 + 1;
+  const double wgt = (kx == 0 || kx == Kx / 2) ? 1.0 : 2.0;
+  const double kxv = pc.two_pi_over_L[0] * kx;
+  const double kxd = (kx == Kx / 2) ? 0.0 : kxv;
+  for (int e = threadIdx.x; e < Kz * yb; e += blockDim.x) {
+    const int yl = e % yb, z = e / yb;
+    const int ny = y0 + yl;
+    const int ay = min(ny, Ky - ny), az = min(z, Kz - z);
+    const double kyv = pc.two_pi_over_L[1] * (ny <= Ky / 2 ? ny : ny - Ky);
+    const double kzv = pc.two_pi_over_L[2] * (z <= Kz / 2 ? z : z - Kz);
+    const double kyd = (2 * ny == Ky) ? 0.0 : kyv;
+    const double kzd = (2 * z == Kz) ? 0.0 : kzv;
+    const double Gv = G[((size_t)kx * Kyh + ay) * Kzh + az];
+    const cpx<T> q = buf[z * w3 + yl];
+    const double s2 = (double)q.x * (double)q.x + (double)q.y * (double)q.y;
+    const double t = wgt * Gv * s2;
+    const double k2 = kxv * kxv + kyv * kyv + kzv * kzv;
+    const double c = (k2 > 0.0) ? 2.0 * (1.0 + k2 * pc.inv_4beta2) / k2 : 0.0;
+    acc[0] += t;
+    acc[1] += t * (1.0 - c * kxv * kxv);
+    acc[2] += t * (1.0 - c * kyv * kyv);
+    acc[3] += t * (1.0 - c * kzv * kzv);
+    acc[4] += t * (-c * kxd * kyd);
+    acc[5] += t * (-c * kxd * kzd);
+    acc[6] += t * (-c * kyd * kzd);
+    // -i k' G Q^ = k' G (q.y, -q.x)
+    const T gx = (T)(Gv * kxd), gy = (T)(Gv * kyd), gz = (T)(Gv * kzd);
+    buf[z * w3 + yl] = cpx<T>{gx * q.y, -gx * q.x};
+    buf[z * w3 + yb + yl] = cpx<T>{gy * q.y, -gy * q.x};
+    buf[z * w3 + 2 * yb + yl] = cpx<T>{gz * q.y, -gz * q.x};
+  }
+  __syncthreads();
+  fft_rows<T, true, kEPT>(buf, w3, Kz, 1, w3, true, tw, g.twN);
+  for (int e = threadIdx.x; e < Kz * w3; e += blockDim.x) {
+    const int c = e % w3, z = e / w3;
+    const int a = c / yb, yl = c % yb;
+    fspec[(((size_t)a * Kh + kx) * Kz + z) * Ky + y0 + yl] = buf[z * w3 + c];
+  }
+
+  // deterministic block reduction of the 7 FP64 partial sums
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    double v = acc[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wave][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    double v = 0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) v += red[w][threadIdx.x];
+    partials[(size_t)blockIdx.x * 8 + threadIdx.x] = v;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Final FP64 reduction of the z-pass partials (fixed tree: deterministic).
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partials, int nblk, double pre,
+                                                double* __restrict__ energy, double* __restrict__ virial) {
+  __shared__ double red[7][256];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    double a = 0.0;
+    for (int b = t; b < nblk; b += 256) a += partials[(size_t)b * 8 + c];
+    red[c][t] = a;
+  }
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+#pragma unroll
+      for (int c = 0; c < 7; ++c) red[c][t] += red[c][t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) *energy = pre * red[0][0];
+  if (t >= 1 && t < 7 && virial) virial[t - 1] = pre * red[t][0];
+}
+
+// ----------------------------------------------------------------------------
+// Inverse complex-to-real transform along x of the field
+// rows a pencil's particles need, then force interpolation with the same
+// assignment weights as the spread.  One workgroup owns the particles whose
+// stencil starts in rows y in [y0, y0+gcy), z in [z0, z0+gcz); it loads rows
+// [y0, y0+gcy+p-1) x [z0, z0+gcz+p-1) (mod K) of one field at a time, so each
+// force component is written exactly once by one thread.
+// ----------------------------------------------------------------------------
+template <typename T, int P>
+__global__ void __launch_bounds__(1024) k_ifftx_gather(const cpx<T>* __restrict__ fspec, const T4<T>* __restrict__ sorted,
+                                                       const int* __restrict__ sidx, const int* __restrict__ perm, const int* __restrict__ bin_start,
+                                                       T* __restrict__ ion_f, T* __restrict__ wc_f, int64_t n_ion,
+                                                       T fscale, int accumulate, const cpx<T>* __restrict__ twg, Geo g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2], Kh = g.Kh;
+  const int RY = g.gcy + P - 1, RZ = g.gcz + P - 1;
+  const int nrows = RY * RZ, nrc = (nrows + 1) >> 1;
+  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem);
+  cpx<T>* tw = tile + nrc * Kx;
+  __shared__ Ranges R;
+
+  const int py = blockIdx.x % g.gpy, pz = blockIdx.x / g.gpy;
+  const int y0 = py * g.gcy, z0 = pz * g.gcz;
+  for (int e = threadIdx.x; e < g.twN; e += blockDim.x) tw[e] = twg[e];
+  if (threadIdx.x == 0) build_ranges(R, bin_start, g, z0, g.gcz, y0 >> 2, g.gcy >> 2);
+  __syncthreads();
+  const int total = R.pre[R.n];
+  const T* tile_r = reinterpret_cast<const T*>(tile);
+
+  for (int a = 0; a < 3; ++a) {
+    const cpx<T>* fs = fspec + (size_t)a * Kh * Kz * Ky;
+    for (int e = threadIdx.x; e < nrc * Kh; e += blockDim.x) {
+      const int cr = e % nrc, k = e / nrc;
+      const int r0 = 2 * cr, r1 = 2 * cr + 1;
+      const int gy0 = wrapi(y0 + r0 % RY, Ky), gz0 = wrapi(z0 + r0 / RY, Kz);
+      cpx<T> A = fs[((size_t)k * Kz + gz0) * Ky + gy0];
+      cpx<T> B = {(T)0, (T)0};
+      if (r1 < nrows) {
+        const int gy1 = wrapi(y0 + r1 % RY, Ky), gz1 = wrapi(z0 + r1 / RY, Kz);
+        B = fs[((size_t)k * Kz + gz1) * Ky + gy1];
+      }
+      if (k == 0 || k == Kx / 2) { A.y = (T)0; B.y = (T)0; }
+      cpx<T>* zr = tile + cr * Kx;
+      zr[k] = cpx<T>{A.x - B.y, A.y + B.x};
+      if (k > 0 && k < Kx / 2) zr[Kx - k] = cpx<T>{A.x + B.y, B.x - A.y};
+    }
+    __syncthreads();
+    fft_rows<T, true, kEPT>(tile, nrc, Kx, Kx, 1, false, tw, g.twN);
+
+    for (int v = threadIdx.x; v < total; v += blockDim.x) {
+      const int idx = range_index(R, v);
+      const T4<T> pt = sorted[idx];
+      const int sp = sidx[idx];
+      const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
+      T wx[P], wy[P], wz[P];
+      bspline_weights<T, P>(pt.x, wx);
+      bspline_weights<T, P>(pt.y, wy);
+      bspline_weights<T, P>(pt.z, wz);
+      T acc = (T)0;
+#pragma unroll
+      for (int tz = 0; tz < P; ++tz) {
+        T sy_acc = (T)0;
+#pragma unroll
+        for (int ty = 0; ty < P; ++ty) {
+          const int row = (sz - z0 + tz) * RY + (sy - y0 + ty);
+          const T* rp = tile_r + 2 * (row >> 1) * Kx + (row & 1);
+          T sx_acc = (T)0;
+#pragma unroll
+          for (int tx = 0; tx < P; ++tx) {
+            int gx = sx + tx;
+            if (gx >= Kx) gx -= Kx;
+            sx_acc += wx[tx] * rp[2 * gx];
+          }
+          sy_acc += wy[ty] * sx_acc;
+        }
+        acc += wz[tz] * sy_acc;
+      }
+      const T f = fscale * pt.w * acc;
+      const int src = perm[idx];
+      T* out = (src < n_ion) ? (ion_f + 3 * (int64_t)src) : (wc_f + 3 * ((int64_t)src - n_ion));
+      out[a] = accumulate ? out[a] + f : f;
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// FP64 optimal influence function for ik-differentiation (per box).
+//   G(k) = sum_m (k.k_m) U^2(k_m) phi(k_m) / (|k|^2 [sum_m U^2(k_m)]^2),
+//   k_m = k + 2 pi m / h, U(k) = prod_a sinc(k_a h_a / 2)^p,
+//   phi(k) = 4 pi exp(-k^2 / (4 beta^2)) / k^2.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double sinc_alias(int n, int K, int m) {
+  // sinc(pi (n/K + m)) with sin(pi(n/K + m)) = (-1)^m sin(pi n/K)
+  if (n == 0) return (m == 0) ? 1.0 : 0.0;
+  const double x = (double)n / (double)K + (double)m;
+  const double s = sinpi((double)n / (double)K);
+  return ((m & 1) ? -s : s) / (M_PI * x);
+}
+
+__global__ void k_influence(double* __restrict__ G, Geo g, double Lx, double Ly, double Lz, double beta, int p,
+                            int alias) {
+  const int Kxh = g.K[0] / 2 + 1, Kyh = g.K[1] / 2 + 1, Kzh = g.K[2] / 2 + 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Kxh * Kyh * Kzh) return;
+  const int az = (int)(i % Kzh);
+  const int ay = (int)((i / Kzh) % Kyh);
+  const int ax = (int)(i / ((int64_t)Kzh * Kyh));
+  const int n[3] = {ax, ay, az};
+  const double L[3] = {Lx, Ly, Lz};
+  double k[3];
+  for (int a = 0; a < 3; ++a) k[a] = 2.0 * M_PI * n[a] / L[a];
+  const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+  if (k2 == 0.0) {
+    G[i] = 0.0;
+    return;
+  }
+  const double inv4b2 = 1.0 / (4.0 * beta * beta);
+  double u2[3][9];
+  double km[3][9];
+  for (int a = 0; a < 3; ++a) {
+    for (int m = -alias; m <= alias; ++m) {
+      double s = sinc_alias(n[a], g.K[a], m);
+      double s2 = s * s, sp = 1.0;
+      for (int t = 0; t < p; ++t) sp *= s2;
+      u2[a][m + alias] = sp;
+      km[a][m + alias] = 2.0 * M_PI * ((double)n[a] + (double)m * g.K[a]) / L[a];
+    }
+  }
+  double num = 0.0, den = 0.0;
+  for (int mx = 0; mx <= 2 * alias; ++mx)
+    for (int my = 0; my <= 2 * alias; ++my)
+      for (int mz = 0; mz <= 2 * alias; ++mz) {
+        const double u = u2[0][mx] * u2[1][my] * u2[2][mz];
+        den += u;
+        if (u == 0.0) continue;
+        const double kx = km[0][mx], ky = km[1][my], kz = km[2][mz];
+        const double kk = kx * kx + ky * ky + kz * kz;
+        const double phi = 4.0 * M_PI * exp(-kk * inv4b2) / kk;
+        num += (k[0] * kx + k[1] * ky + k[2] * kz) * u * phi;
+      }
+  G[i] = num / (k2 * den * den);
+}
+
+// ----------------------------------------------------------------------------
+// Backward of E with respect to positions: grad = -g * F.
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ void k_scale_grad(const double* __restrict__ gE, const T* __restrict__ f, T* __restrict__ out, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  out[i] = (T)(-(*gE) * (double)f[i]);
+}
+
+}  // namespace dplr

@@ -1,0 +1,159 @@
+"""GPU parity of the PPPM-ik path (through the C ABI) against the oracles.
+
+FP64 plans must reproduce the NumPy PPPM oracle to rounding (the bar is 1e-9
+relative; the discrete operator is identical) and, at a refined mesh and
+order, the direct Ewald oracle to 1e-9.  FP32 plans are compared with the
+oracles evaluated at the FP32-rounded inputs promoted to FP64, so input
+rounding is not charged to the kernels.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import systems
+from oracle import pppm
+
+pytestmark = pytest.mark.gpu
+
+KE = systems.COULOMB_K
+BETA = systems.BETA
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    return torch
+
+
+def run_gpu(torch, sys, mesh, order, precision, alias=2, flags=0, plan=None):
+    import paper_2504_15508_amd as dl
+    if isinstance(mesh, int):
+        mesh = (mesh,) * 3
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    if plan is None:
+        plan = dl.Plan(mesh, order=order, beta=BETA, coulomb_k=KE, precision=precision,
+                       alias_range=alias, capacity=sys.n, flags=flags)
+        plan.set_box(sys.box)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    E, fi, fw, W = plan.compute(t(sys.ion_pos), t(sys.ion_q), t(sys.wc_pos), t(sys.wc_q))
+    torch.cuda.synchronize()
+    return (float(E.item()), fi.double().cpu().numpy(), fw.double().cpu().numpy(),
+            W.cpu().numpy(), plan)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def check_vs_pppm(torch, sys, mesh, order, precision, tol_f, tol_e, tol_w, alias=2):
+    E, fi, fw, W, _ = run_gpu(torch, sys, mesh, order, precision, alias)
+    ref = sys.rounded(np.float32) if precision == "fp32" else sys
+    K = (mesh,) * 3 if isinstance(mesh, int) else mesh
+    E0, F0, W0 = pppm.pppm(ref.all_pos(), ref.all_q(), ref.box, K, order, BETA, KE, alias)
+    F = np.concatenate([fi, fw])
+    print(f"{sys.name} K={K} p={order} {precision}: dE={abs(E - E0) / abs(E0):.2e} "
+          f"dF={rel(F, F0):.2e} dW={np.abs(W - W0).max() / abs(E0):.2e}", flush=True)
+    assert abs(E - E0) <= tol_e * abs(E0)
+    assert rel(F, F0) <= tol_f
+    assert np.abs(W - W0).max() <= tol_w * abs(E0)
+    return E, F, W
+
+
+def test_influence_table_fp64(torch_dev):
+    import paper_2504_15508_amd as dl
+    box = np.array([12.42, 14.0, 10.5])
+    plan = dl.Plan((32, 16, 64), order=5, beta=BETA, coulomb_k=KE, precision="fp64", capacity=1)
+    plan.set_box(box)
+    torch_dev.cuda.synchronize()
+    G = plan.debug_buffer(dl._lib.BUF_INFLUENCE).cpu().numpy()
+    G0 = pppm.influence(box, (32, 16, 64), BETA, 5)
+    ref = G0[:17, :9, :33]
+    assert np.abs(G - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_spectrum_matches_oracle(torch_dev, precision):
+    import paper_2504_15508_amd as dl
+    s = systems.workload(1).system()
+    _, _, _, _, plan = run_gpu(torch_dev, s, 32, 5, precision)
+    S = plan.debug_buffer(dl._lib.BUF_SPECTRUM).cpu().numpy()      # [kx][kz][ky]
+    ref = s.rounded(np.float32) if precision == "fp32" else s
+    Q = pppm.spread(ref.all_pos(), ref.all_q(), ref.box, (32, 32, 32), 5)
+    # the buffer holds the mesh transformed along x and y (z is done in the Poisson pass)
+    Qh = np.fft.fft(np.fft.fft(Q, axis=0), axis=1)[:17].transpose(0, 2, 1)   # [kx][z][ky]
+    # FP64 plans accumulate the mesh in 64-bit fixed point with a 2^-40 quantum
+    tol = 1e-11 if precision == "fp64" else 2e-6
+    err = float(np.abs(S - Qh).max() / np.abs(Qh).max())
+    print(f"spectrum {precision}: max rel err {err:.2e}")
+    assert err <= tol
+
+
+def test_fp64_config1_matches_pppm_oracle(torch_dev):
+    s = systems.workload(1).system()
+    check_vs_pppm(torch_dev, s, 32, 5, "fp64", 1e-9, 1e-9, 1e-9)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 6, 7, 8])
+def test_fp64_orders_match_pppm_oracle(torch_dev, order):
+    s = systems.workload(1).system()
+    check_vs_pppm(torch_dev, s, 32, order, "fp64", 1e-9, 1e-9, 1e-9)
+
+
+def test_fp64_noncubic_mesh_and_box(torch_dev):
+    s = systems.water_box(100, 14.0, seed=99)
+    s.box = np.array([14.0, 18.0, 11.0])
+    s.ion_pos = np.mod(s.ion_pos, s.box)
+    s.wc_pos = np.mod(s.wc_pos, s.box)
+    check_vs_pppm(torch_dev, s, (32, 64, 16), 5, "fp64", 1e-9, 1e-9, 1e-9)
+
+
+def test_fp64_refined_matches_ewald_1e9(torch_dev, ewald):
+    s = systems.workload(1).system()
+    E, fi, fw, W, _ = run_gpu(torch_dev, s, 64, 8, "fp64")
+    e0, w0, fi0, fw0 = ewald.system_recip(s, BETA, KE)
+    F, F0 = np.concatenate([fi, fw]), np.concatenate([fi0, fw0])
+    print(f"refined vs Ewald: dE={abs(E - e0) / abs(e0):.2e} dF={rel(F, F0):.2e} "
+          f"dW={np.abs(W - w0).max() / abs(e0):.2e}")
+    assert abs(E - e0) <= 1e-9 * abs(e0)
+    assert rel(F, F0) <= 1e-9
+    assert np.abs(W - w0).max() <= 1e-9 * abs(e0)
+
+
+# FP32 bar against the FP64 oracle at identical (FP32-rounded) inputs: the
+# spread sums FP32 products exactly, so the error comes from FP32 rounding in
+# the B-spline weights and products (~1e-7 relative each), the three FFT
+# passes (~eps * log2(K^3) ~ 1e-6 of the largest mode) and the 125-term
+# gather; water's near-cancelling intramolecular forces amplify relative
+# force error ~10x over the mesh error.  Bar: 1e-5 relative force RMSE,
+# 2e-6 relative energy and virial (largest virial component / |E|).
+FP32_TOL_F, FP32_TOL_E = 1e-5, 2e-6
+
+
+def test_fp32_config1_matches_pppm_oracle(torch_dev):
+    s = systems.workload(1).system()
+    check_vs_pppm(torch_dev, s, 32, 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
+
+
+def test_fp32_config2_matches_pppm_oracle(torch_dev):
+    s = systems.workload(2).system()
+    check_vs_pppm(torch_dev, s, 64, 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
+
+
+def test_zero_net_force_and_mesh_shift(torch_dev):
+    s = systems.workload(1).system()
+    E, fi, fw, W, _ = run_gpu(torch_dev, s, 32, 5, "fp64")
+    F = np.concatenate([fi, fw])
+    assert np.linalg.norm(F.sum(0)) <= 1e-10 * np.abs(F).max()
+    h = s.box / 32
+    t = s.rounded(np.float64)
+    shift = h * np.array([5, -3, 9])
+    t.ion_pos = np.mod(t.ion_pos + shift, s.box)
+    t.wc_pos = np.mod(t.wc_pos + shift, s.box)
+    E2, fi2, fw2, W2, _ = run_gpu(torch_dev, t, 32, 5, "fp64")
+    # exact for the method; the FP64 plan's 2^-40 fixed-point mesh quantum and
+    # the rounding of r + shift leave ~1e-12 differences
+    assert abs(E2 - E) <= 1e-10 * abs(E)
+    assert np.abs(np.concatenate([fi2, fw2]) - F).max() <= 1e-10 * np.abs(F).max()
