@@ -68,10 +68,13 @@ def kernel_bytes(stage: str, N: int, K: int, order: int) -> float:
         return 2 * spec
     if stage == "fftz_poisson":
         return spec + mesh_g + 3 * spec
-    if stage == "ffty_inv":
+    if stage == "ffty_inv_reduce":
         return 2 * 3 * spec
-    if stage == "ifftx_gather":
-        return 3 * spec + part + N * 4 + N * 12
+    if stage == "ifftx":
+        return 3 * spec + 3 * 4 * K ** 3
+    if stage == "gather":
+        # fields read once + particles (d, q, stencil start, perm) + forces
+        return 3 * 4 * K ** 3 + part + N * 4 + N * 12
     return 0.0
 
 

@@ -89,11 +89,20 @@ __device__ __forceinline__ void dft_small(cpx<T>* v) {
 // tw holds exp(-2 pi i k / twN), k < twN, with N dividing twN.
 // EPT bounds the elements per thread: nrows * N <= EPT * blockDim.x.
 // ---------------------------------------------------------------------------
-template <typename T, int R, bool INV, int EPT>
+// Row transforms (estride == 1) keep one padding element after every 16, so
+// the stride-R writes of the early stages do not pile onto a few LDS banks:
+// element e of a row lives at e + e / 16 (lds_pad).  Column transforms
+// (estride > 1) are laid out unpadded: their lanes already walk consecutive
+// words.
+__device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
+__host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4); }
+
+template <typename T, int R, bool INV, int EPT, bool PAD>
 __device__ __forceinline__ void fft_stage(cpx<T>* buf, int nrows, int N, int rstride, int estride,
                                           bool rows_fast, int Ns, const cpx<T>* tw, int twN) {
   constexpr int BPT = (EPT + R - 1) / R;
   const int nb = N / R;
+  const int lnb = 31 - __clz(nb);  // nb is a power of two
   const int total = nrows * nb;
   cpx<T> v[BPT][R];
 #pragma unroll
@@ -101,10 +110,13 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int nrows, int N, int rst
     const int b = threadIdx.x + c * blockDim.x;
     if (b < total) {
       int row, j;
-      if (rows_fast) { row = b % nrows; j = b / nrows; } else { j = b % nb; row = b / nb; }
+      if (rows_fast) { j = b / nrows; row = b - j * nrows; } else { j = b & (nb - 1); row = b >> lnb; }
       const cpx<T>* base = buf + row * rstride;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[c][r] = base[(j + r * nb) * estride];
+      for (int r = 0; r < R; ++r) {
+        const int e = j + r * nb;
+        v[c][r] = base[PAD ? lds_pad(e) : e * estride];
+      }
     }
   }
   __syncthreads();
@@ -114,8 +126,8 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int nrows, int N, int rst
     const int b = threadIdx.x + c * blockDim.x;
     if (b < total) {
       int row, j;
-      if (rows_fast) { row = b % nrows; j = b / nrows; } else { j = b % nb; row = b / nb; }
-      const int k = j % Ns;
+      if (rows_fast) { j = b / nrows; row = b - j * nrows; } else { j = b & (nb - 1); row = b >> lnb; }
+      const int k = j & (Ns - 1);
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -126,9 +138,12 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int nrows, int N, int rst
       }
       dft_small<T, R, INV>(v[c]);
       cpx<T>* base = buf + row * rstride;
-      const int o = (j / Ns) * Ns * R + k;
+      const int o = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) base[(o + r * Ns) * estride] = v[c][r];
+      for (int r = 0; r < R; ++r) {
+        const int e = o + r * Ns;
+        base[PAD ? lds_pad(e) : e * estride] = v[c][r];
+      }
     }
   }
   __syncthreads();
@@ -136,18 +151,18 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int nrows, int N, int rst
 
 // Full transform: radix-8 stages while that leaves a length of 4 or more
 // (or exactly 1), radix-4 for the rest.  N is a power of two >= 4.
-template <typename T, bool INV, int EPT>
+template <typename T, bool INV, int EPT, bool PAD = false>
 __device__ void fft_rows(cpx<T>* buf, int nrows, int N, int rstride, int estride, bool rows_fast,
                          const cpx<T>* tw, int twN) {
   int lg = 31 - __clz(N);
   int Ns = 1;
   while (lg > 0) {
     if (lg >= 3 && lg - 3 != 1) {
-      fft_stage<T, 8, INV, EPT>(buf, nrows, N, rstride, estride, rows_fast, Ns, tw, twN);
+      fft_stage<T, 8, INV, EPT, PAD>(buf, nrows, N, rstride, estride, rows_fast, Ns, tw, twN);
       Ns *= 8;
       lg -= 3;
     } else {
-      fft_stage<T, 4, INV, EPT>(buf, nrows, N, rstride, estride, rows_fast, Ns, tw, twN);
+      fft_stage<T, 4, INV, EPT, PAD>(buf, nrows, N, rstride, estride, rows_fast, Ns, tw, twN);
       Ns *= 4;
       lg -= 2;
     }

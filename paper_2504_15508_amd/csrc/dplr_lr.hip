@@ -74,8 +74,8 @@ struct dplr_lr_plan_s {
   double box[3] = {0, 0, 0};
   bool has_box = false;
   size_t lds_budget = 65536;
-  size_t lds_spread = 0, lds_ffty = 0, lds_z = 0, lds_gather = 0;
-  int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_gather = 256;
+  size_t lds_spread = 0, lds_ffty = 0, lds_z = 0, lds_ifftx = 0;
+  int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_ifftx = 256;
   // device workspace
   int* bin_count = nullptr;
   int* bin_start = nullptr;
@@ -88,6 +88,7 @@ struct dplr_lr_plan_s {
   int* sidx = nullptr;
   void* spec = nullptr;
   void* fspec = nullptr;
+  void* field = nullptr;   // real fields [Kz][Ky][Kx] x (Ex, Ey, Ez)
   double* G = nullptr;
   double* partials = nullptr;
   void* twiddle = nullptr;
@@ -106,7 +107,7 @@ struct dplr_lr_plan_s {
 namespace {
 
 const char* const kStageNames[] = {"bin_count", "bin_scan", "bin_scatter", "spread_fftx", "ffty_fwd",
-                                   "fftz_poisson", "ffty_inv", "ifftx_gather", "reduce"};
+                                   "fftz_poisson", "ffty_inv_reduce", "ifftx", "gather"};
 constexpr int kNumStages = 9;
 
 hipEvent_t prof_event(dplr_lr_plan p) {
@@ -172,8 +173,10 @@ bool choose_geometry(dplr_lr_plan p) {
   for (auto& c : cand) {
     const int cy = c[0], cz = c[1];
     if (cy > Ky || cz > Kz || (cy * cz) % 2) continue;
-    // 64-bit fixed-point accumulators, converted in place to complex pairs
-    const size_t b = (size_t)cy * cz * Kx * sizeof(long long) + twb;
+    // 64-bit fixed-point accumulators, converted in place to padded complex pairs
+    const size_t accb = (size_t)cy * cz * Kx * sizeof(long long);
+    const size_t cpxb = (size_t)(cy * cz / 2) * (padded_len(Kx) + 1) * cs;
+    const size_t b = std::max(accb, cpxb) + twb;
     const long long elems = (long long)cy * cz * Kx;
     if (b <= budget && elems <= 16LL * 1024) {
       g.scy = cy; g.scz = cz; p->lds_spread = b;
@@ -186,28 +189,21 @@ bool choose_geometry(dplr_lr_plan p) {
   p->thr_spread = std::max(DPLR_SPREAD_MIN_THREADS, round_threads((long)g.scy * g.scz / 2 * Kx));
   while ((long)p->thr_spread * 16 < (long)g.scy * g.scz * Kx && p->thr_spread < 1024) p->thr_spread += 64;
 
-  const int gcand[][2] = {{8, 4}, {4, 4}, {8, 2}, {4, 2}, {4, 1}};
-  g.gcy = 0;
-  for (auto& c : gcand) {
-    const int cy = c[0], cz = c[1];
-    if (cy > Ky || cz > Kz) continue;
-    const int nrows = (cy + P - 1) * (cz + P - 1);
-    const int nrc = (nrows + 1) / 2;
-    const size_t b = (size_t)nrc * Kx * cs + twb;
-    if (b <= budget && (long)nrc * Kx <= (long)kEPT * 1024) {
-      g.gcy = cy; g.gcz = cz; p->lds_gather = b;
-      p->thr_gather = std::max(DPLR_GATHER_MIN_THREADS, round_threads((long)nrc * Kx));
-      break;
-    }
-  }
-  if (!g.gcy) return false;
-  g.gpy = Ky / g.gcy; g.gpz = Kz / g.gcz;
+  // inverse x pass: xyb rows of y of the three fields per block
+  g.xyb = std::min(16, Ky);
+  while (g.xyb > 2 && ((size_t)(3 * g.xyb / 2) * (padded_len(Kx) + 1) * cs + twb > budget ||
+                       (long)(3 * g.xyb / 2) * Kx > (long)kEPT * 512))
+    g.xyb /= 2;
+  p->lds_ifftx = (size_t)(3 * g.xyb / 2) * (padded_len(Kx) + 1) * cs + twb;
+  p->thr_ifftx = std::max(round_threads((long)(3 * g.xyb / 2) * Kx), ((3 * g.xyb / 2 + 63) / 64) * 64);
+  if (p->thr_ifftx > 512) return false;
 
-  // y pass: blocks of zb contiguous rows, about 4096 complex elements
-  g.zb = std::max(1, std::min(Kz, 4096 / Ky));
-  while (g.zb > 1 && (size_t)g.zb * Ky * cs + twb > budget) g.zb /= 2;
-  p->lds_ffty = (size_t)g.zb * Ky * cs + twb;
+  // y pass: blocks of zb contiguous rows, about 1024 complex elements
+  g.zb = std::max(1, std::min(Kz, 1024 / Ky));
+  while (g.zb > 1 && (size_t)g.zb * (padded_len(Ky) + 1) * cs + twb > budget) g.zb /= 2;
   p->thr_ffty = round_threads((long)g.zb * Ky);
+  // the inverse pass also hosts the final reduction: 7 doubles per thread
+  p->lds_ffty = std::max((size_t)g.zb * (padded_len(Ky) + 1) * cs + twb, (size_t)7 * p->thr_ffty * sizeof(double));
 
   // z pass: yb columns x Kz x 3 fields
   g.yb = std::min(16, Ky);
@@ -253,7 +249,6 @@ void set_lds_attrs(dplr_lr_plan p) {
 #define DPLR_ATTR(PP)                                                        \
   case PP:                                                                   \
     attr((const void*)k_spread_fftx<T, PP>, p->lds_spread);                  \
-    attr((const void*)k_ifftx_gather<T, PP>, p->lds_gather);                 \
     break;
     DPLR_ATTR(2) DPLR_ATTR(3) DPLR_ATTR(4) DPLR_ATTR(5) DPLR_ATTR(6) DPLR_ATTR(7) DPLR_ATTR(8)
 #undef DPLR_ATTR
@@ -270,6 +265,7 @@ void set_lds_attrs(dplr_lr_plan p) {
   attr((const void*)k_ffty<T, false>, p->lds_ffty);
   attr((const void*)k_ffty<T, true>, p->lds_ffty);
   attr((const void*)k_fftz_poisson<T>, p->lds_z);
+  attr((const void*)k_ifftx<T>, p->lds_ifftx);
 }
 
 template <typename T, int P>
@@ -300,7 +296,7 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
     {
       ProfScope ps(p, 1);
       if (n > 0) {
-        hipLaunchKernelGGL(k_bin_colscan, dim3((g.nbins + 63) / 64), dim3(64), 0, s, p->bin_hist, p->bin_count,
+        hipLaunchKernelGGL(k_bin_colscan, dim3((g.nbins + 63) / 64), dim3(1024), 0, s, p->bin_hist, p->bin_count,
                            nblk, g.nbins);
       } else {
         hipLaunchKernelGGL(k_fill_int, dim3((g.nbins + 255) / 256), dim3(256), 0, s, p->bin_count, g.nbins, 0);
@@ -339,7 +335,8 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
   }
   {
     ProfScope ps(p, 4);
-    hipLaunchKernelGGL((k_ffty<T, false>), dim3(g.Kh * (g.K[2] / g.zb)), dim3(p->thr_ffty), p->lds_ffty, s, spec, tw, g);
+    hipLaunchKernelGGL((k_ffty<T, false>), dim3(g.Kh * (g.K[2] / g.zb)), dim3(p->thr_ffty), p->lds_ffty, s, spec, tw, g,
+                       (const double*)nullptr, 0.0, (double*)nullptr, (double*)nullptr);
   }
   PoissonConsts pc;
   for (int a = 0; a < 3; ++a) pc.two_pi_over_L[a] = 2.0 * M_PI / p->box[a];
@@ -349,23 +346,30 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
     hipLaunchKernelGGL((k_fftz_poisson<T>), dim3(g.nzblk), dim3(p->thr_z), p->lds_z, s, spec, fspec, p->G,
                        p->partials, tw, g, pc);
   }
+  const double V = p->box[0] * p->box[1] * p->box[2];
+  const bool want_virial = !(p->cfg.flags & DPLR_LR_NO_VIRIAL) && virial;
   {
     ProfScope ps(p, 6);
     hipLaunchKernelGGL((k_ffty<T, true>), dim3(3 * g.Kh * (g.K[2] / g.zb)), dim3(p->thr_ffty), p->lds_ffty, s,
-                       fspec, tw, g);
+                       fspec, tw, g, (const double*)p->partials, p->cfg.coulomb_k / (2.0 * V), energy,
+                       want_virial ? virial : (double*)nullptr);
   }
-  const double V = p->box[0] * p->box[1] * p->box[2];
   if (n > 0) {
-    ProfScope ps(p, 7);
-    hipLaunchKernelGGL((k_ifftx_gather<T, P>), dim3(g.gpy * g.gpz), dim3(p->thr_gather), p->lds_gather, s, fspec,
-                       sorted, p->sidx, p->perm, p->bin_start, (T*)ion_force, (T*)wc_force, n_ion, (T)(p->cfg.coulomb_k / V),
-                       (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0, tw, g);
-  }
-  const bool want_virial = !(p->cfg.flags & DPLR_LR_NO_VIRIAL) && virial;
-  {
-    ProfScope ps(p, 8);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, p->partials, g.nzblk, p->cfg.coulomb_k / (2.0 * V),
-                       energy, want_virial ? virial : (double*)nullptr);
+    {
+      ProfScope ps(p, 7);
+      hipLaunchKernelGGL((k_ifftx<T>), dim3(g.K[2] * (g.K[1] / g.xyb)), dim3(p->thr_ifftx), p->lds_ifftx, s, fspec,
+                         reinterpret_cast<F3<T>*>(p->field), tw, g);
+    }
+    {
+      ProfScope ps(p, 8);
+      constexpr int kXcd = 8;  // MI355X: 8 XCDs, blocks dealt round-robin
+      const int per_block = 4 * (64 / P);
+      const int nchunks = (int)((n + per_block - 1) / per_block);
+      const int nblk = (nchunks + kXcd - 1) / kXcd * kXcd;
+      hipLaunchKernelGGL((k_gather<T, P>), dim3(nblk), dim3(256), 0, s, reinterpret_cast<const F3<T>*>(p->field),
+                         sorted, p->sidx, p->perm, (int)n, nchunks, (T*)ion_force, (T*)wc_force, n_ion,
+                         (T)(p->cfg.coulomb_k / V), (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0, kXcd, g);
+    }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
@@ -462,6 +466,7 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
   DPLR_ALLOC(p->sidx, sizeof(int) * cap, "stencil starts");
   DPLR_ALLOC(p->spec, cs * nspec, "spectrum");
   DPLR_ALLOC(p->fspec, 3 * cs * nspec, "field spectra");
+  DPLR_ALLOC(p->field, 3 * ts * (size_t)g.K[0] * g.K[1] * g.K[2], "fields");
   DPLR_ALLOC(p->G, sizeof(double) * ng, "influence");
   DPLR_ALLOC(p->partials, sizeof(double) * 8 * g.nzblk, "partials");
   DPLR_ALLOC(p->twiddle, cs * g.twN, "twiddles");

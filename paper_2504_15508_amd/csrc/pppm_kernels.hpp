@@ -29,12 +29,11 @@ struct Geo {
   int nbins;     // Kz * NQ
   int scy, scz;  // spread pencil cross-section (y, z); the pencil spans all x
   int spy, spz;  // spread pencil counts
-  int gcy, gcz;  // gather pencil cross-section
-  int gpy, gpz;  // gather pencil counts
   int zb;        // rows per block of the y-transform pass
   int yb;        // columns per block of the z-transform pass
   int twN;       // twiddle table length (max K)
   int nzblk;     // z-pass blocks
+  int xyb;       // y rows per block of the inverse x pass
 };
 
 struct PoissonConsts {
@@ -43,6 +42,26 @@ struct PoissonConsts {
 };
 
 constexpr int kEPT = 16;  // FFT elements per thread bound
+
+// Copies n contiguous elements from global memory to LDS with U loads in
+// flight per thread before any of them is stored (a loop whose trip count
+// the compiler cannot see would otherwise wait for each load in turn).
+template <int U, typename V>
+__device__ __forceinline__ void copy_g2s(V* __restrict__ dst, const V* __restrict__ src, int n) {
+  for (int base = threadIdx.x; base < n; base += U * blockDim.x) {
+    V r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * blockDim.x;
+      if (e < n) r[u] = src[e];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * blockDim.x;
+      if (e < n) dst[e] = r[u];
+    }
+  }
+}
 
 __device__ __forceinline__ int wrapi(int v, int K) {
   v %= K;
@@ -177,28 +196,36 @@ __global__ void k_fill_int(int* __restrict__ a, int n, int v) {
 }
 
 // Per bin: exclusive scan of the chunk counts (in place) and the bin total.
-__global__ void __launch_bounds__(64) k_bin_colscan(int* __restrict__ hist, int* __restrict__ total, int nblk,
-                                                    int nbins) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nbins) return;
+// A block of 1024 threads handles 64 bins; its 16 groups of 64 lanes split
+// the chunks into 16 consecutive ranges whose sums are combined in LDS.
+__global__ void __launch_bounds__(1024) k_bin_colscan(int* __restrict__ hist, int* __restrict__ total, int nblk,
+                                                      int nbins) {
+  __shared__ int gsum[16][64];
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int b = blockIdx.x * 64 + lane;
+  const int per = (nblk + 15) / 16;
+  const int k0 = min(nblk, grp * per), k1 = min(nblk, k0 + per);
+  int s = 0;
+  int c[16];
+  const int cnt = k1 - k0;  // at most 16 chunks per group (at most 256 chunks)
+#pragma unroll
+  for (int u = 0; u < 16; ++u) c[u] = (b < nbins && u < cnt) ? hist[(size_t)(k0 + u) * nbins + b] : 0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s += c[u];
+  gsum[grp][lane] = s;
+  __syncthreads();
   int run = 0;
-  int k = 0;
-  for (; k + 8 <= nblk; k += 8) {
-    int c[8];
+  for (int g2 = 0; g2 < grp; ++g2) run += gsum[g2][lane];
+  if (b < nbins) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) c[u] = hist[(size_t)(k + u) * nbins + b];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      hist[(size_t)(k + u) * nbins + b] = run;
-      run += c[u];
+    for (int u = 0; u < 16; ++u) {
+      if (u < cnt) {
+        hist[(size_t)(k0 + u) * nbins + b] = run;
+        run += c[u];
+      }
     }
+    if (grp == 15) total[b] = run;
   }
-  for (; k < nblk; ++k) {
-    const int c = hist[(size_t)k * nbins + b];
-    hist[(size_t)k * nbins + b] = run;
-    run += c;
-  }
-  total[b] = run;
 }
 
 // Exclusive scan of the bin totals (one block of 1024 threads).
@@ -261,25 +288,33 @@ struct Ranges {
   int n;
   int lo[48];
   int pre[49];  // prefix sums of lengths
+  int b[48][2]; // scratch: bin bounds, then particle bounds, per candidate range
 };
 
+// Called by every thread of the block (contains barriers).  Each candidate
+// range (up to two per plane) is resolved by its own thread, so the block
+// waits for one round of bin_start loads instead of a chain of them.
 __device__ __forceinline__ void build_ranges(Ranges& R, const int* __restrict__ bin_start, const Geo& g,
                                              int z_lo, int nplanes, int q_lo, int nq) {
-  int n = 0, acc = 0;
-  for (int i = 0; i < nplanes; ++i) {
+  const int t = threadIdx.x;
+  const int qa = wrapi(q_lo, g.NQ);
+  const bool split = qa + nq > g.NQ;
+  const int ncand = nplanes * (split ? 2 : 1);
+  if (t < ncand) {
+    const int i = split ? (t >> 1) : t, j = split ? (t & 1) : 0;
     const int z = wrapi(z_lo + i, g.K[2]);
-    const int qa = wrapi(q_lo, g.NQ);
-    int parts[2][2];
-    int np = 0;
-    if (qa + nq <= g.NQ) {
-      parts[0][0] = qa; parts[0][1] = qa + nq; np = 1;
-    } else {
-      parts[0][0] = qa; parts[0][1] = g.NQ;
-      parts[1][0] = 0; parts[1][1] = qa + nq - g.NQ; np = 2;
-    }
-    for (int j = 0; j < np; ++j) {
-      const int b0 = z * g.NQ + parts[j][0], b1 = z * g.NQ + parts[j][1];
-      const int p0 = bin_start[b0], p1 = bin_start[b1];
+    int q0, q1;
+    if (!split) { q0 = qa; q1 = qa + nq; }
+    else if (j == 0) { q0 = qa; q1 = g.NQ; }
+    else { q0 = 0; q1 = qa + nq - g.NQ; }
+    R.b[t][0] = bin_start[z * g.NQ + q0];
+    R.b[t][1] = bin_start[z * g.NQ + q1];
+  }
+  __syncthreads();
+  if (t == 0) {
+    int n = 0, acc = 0;
+    for (int c = 0; c < ncand; ++c) {
+      const int p0 = R.b[c][0], p1 = R.b[c][1];
       if (p1 > p0) {
         R.lo[n] = p0;
         R.pre[n] = acc;
@@ -287,9 +322,10 @@ __device__ __forceinline__ void build_ranges(Ranges& R, const int* __restrict__ 
         ++n;
       }
     }
+    R.pre[n] = acc;
+    R.n = n;
   }
-  R.pre[n] = acc;
-  R.n = n;
+  __syncthreads();
 }
 
 __device__ __forceinline__ int range_index(const Ranges& R, int v) {
@@ -350,16 +386,19 @@ __global__ void __launch_bounds__(1024) k_spread_fftx(const T4<T>* __restrict__ 
   const int nrows = g.scy * g.scz;
   const int nrc = nrows >> 1;
   long long* acc = reinterpret_cast<long long*>(smem);          // [nrows][Kx]
-  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem);               // [nrc][Kx] after conversion
-  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem + (size_t)nrows * Kx * sizeof(long long));
+  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem);               // [nrc][RS] after conversion
+  const int RS = padded_len(Kx) + 1;                             // odd row stride (banks)
+  const size_t acc_bytes = (size_t)nrows * Kx * sizeof(long long);
+  const size_t cpx_bytes = (size_t)nrc * RS * sizeof(cpx<T>);
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem + (acc_bytes > cpx_bytes ? acc_bytes : cpx_bytes));
   __shared__ Ranges R;
 
   const int py = blockIdx.x % g.spy, pz = blockIdx.x / g.spy;
   const int y0 = py * g.scy, z0 = pz * g.scz;
 
   for (int e = threadIdx.x; e < nrows * Kx; e += blockDim.x) acc[e] = 0;
-  for (int e = threadIdx.x; e < g.twN; e += blockDim.x) tw[e] = twg[e];
-  if (threadIdx.x == 0) {
+  copy_g2s<8>(tw, twg, g.twN);
+  {
     const int nplanes = min(g.scz + P - 1, Kz);
     const int ylo = y0 - (P - 1);
     const int q_lo = (ylo >= 0) ? (ylo >> 2) : -((3 - ylo) >> 2);
@@ -367,38 +406,52 @@ __global__ void __launch_bounds__(1024) k_spread_fftx(const T4<T>* __restrict__ 
     const int nq = min(q_hi - q_lo + 1, g.NQ);
     build_ranges(R, bin_start, g, z0 - (P - 1), nplanes, q_lo, nq);
   }
-  __syncthreads();
 
   const int total = R.pre[R.n];
-  for (int v = threadIdx.x; v < total; v += blockDim.x) {
-    const int idx = range_index(R, v);
-    const T4<T> pt = sorted[idx];
-    const int sp = sidx[idx];
-    const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
-    T wx[P], wy[P], wz[P];
-    bspline_weights<T, P>(pt.x, wx);
-    bspline_weights<T, P>(pt.y, wy);
-    bspline_weights<T, P>(pt.z, wz);
+  constexpr int PB = 4;  // particles fetched per thread before processing
+  for (int v0 = threadIdx.x; v0 < total; v0 += PB * blockDim.x) {
+    T4<T> pts[PB];
+    int sps[PB];
 #pragma unroll
-    for (int tz = 0; tz < P; ++tz) {
-      int gz = sz + tz;
-      if (gz >= Kz) gz -= Kz;
-      const int lz = gz - z0;
-      if (lz < 0 || lz >= g.scz) continue;
-      const T qz = pt.w * wz[tz];
+    for (int u = 0; u < PB; ++u) {
+      const int v = v0 + u * blockDim.x;
+      if (v < total) {
+        const int idx = range_index(R, v);
+        pts[u] = sorted[idx];
+        sps[u] = sidx[idx];
+      }
+    }
 #pragma unroll
-      for (int ty = 0; ty < P; ++ty) {
-        int gy = sy + ty;
-        if (gy >= Ky) gy -= Ky;
-        const int ly = gy - y0;
-        if (ly < 0 || ly >= g.scy) continue;
-        unsigned long long* rp = reinterpret_cast<unsigned long long*>(acc + (size_t)(lz * g.scy + ly) * Kx);
-        const T qyz = qz * wy[ty];
+    for (int u = 0; u < PB; ++u) {
+      if (v0 + u * blockDim.x >= total) continue;
+      const T4<T> pt = pts[u];
+      const int sp = sps[u];
+      const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
+      T wx[P], wy[P], wz[P];
+      bspline_weights<T, P>(pt.x, wx);
+      bspline_weights<T, P>(pt.y, wy);
+      bspline_weights<T, P>(pt.z, wz);
 #pragma unroll
-        for (int tx = 0; tx < P; ++tx) {
-          int gx = sx + tx;
-          if (gx >= Kx) gx -= Kx;
-          atomicAdd(rp + gx, (unsigned long long)to_fixed<T>(qyz * wx[tx]));
+      for (int tz = 0; tz < P; ++tz) {
+        int gz = sz + tz;
+        if (gz >= Kz) gz -= Kz;
+        const int lz = gz - z0;
+        if (lz < 0 || lz >= g.scz) continue;
+        const T qz = pt.w * wz[tz];
+#pragma unroll
+        for (int ty = 0; ty < P; ++ty) {
+          int gy = sy + ty;
+          if (gy >= Ky) gy -= Ky;
+          const int ly = gy - y0;
+          if (ly < 0 || ly >= g.scy) continue;
+          unsigned long long* rp = reinterpret_cast<unsigned long long*>(acc + (size_t)(lz * g.scy + ly) * Kx);
+          const T qyz = qz * wy[ty];
+#pragma unroll
+          for (int tx = 0; tx < P; ++tx) {
+            int gx = sx + tx;
+            if (gx >= Kx) gx -= Kx;
+            atomicAdd(rp + gx, (unsigned long long)to_fixed<T>(qyz * wx[tx]));
+          }
         }
       }
     }
@@ -423,13 +476,13 @@ __global__ void __launch_bounds__(1024) k_spread_fftx(const T4<T>* __restrict__ 
       const int e = threadIdx.x + c * blockDim.x;
       if (c < per && e < nrows * Kx) {
         const int row = e / Kx, x = e - row * Kx;
-        out[2 * ((row >> 1) * Kx + x) + (row & 1)] = from_fixed<T>(v[c]);
+        out[2 * ((row >> 1) * RS + lds_pad(x)) + (row & 1)] = from_fixed<T>(v[c]);
       }
     }
     __syncthreads();
   }
 
-  fft_rows<T, false, kEPT>(tile, nrc, Kx, Kx, 1, false, tw, g.twN);
+  fft_rows<T, false, kEPT, true>(tile, nrc, Kx, RS, 1, false, tw, g.twN);
 
   const int Kh = g.Kh;
   for (int e = threadIdx.x; e < nrows * Kh; e += blockDim.x) {
@@ -438,9 +491,9 @@ __global__ void __launch_bounds__(1024) k_spread_fftx(const T4<T>* __restrict__ 
     const int lz = rest % g.scz;
     const int k = rest / g.scz;
     const int row = lz * g.scy + ly;
-    const cpx<T>* zr = tile + (row >> 1) * Kx;
-    const cpx<T> z1 = zr[k];
-    const cpx<T> z2 = cconj(zr[(Kx - k) & (Kx - 1)]);
+    const cpx<T>* zr = tile + (row >> 1) * RS;
+    const cpx<T> z1 = zr[lds_pad(k)];
+    const cpx<T> z2 = cconj(zr[lds_pad((Kx - k) & (Kx - 1))]);
     cpx<T> out;
     if ((row & 1) == 0) {
       out = cpx<T>{(T)0.5 * (z1.x + z2.x), (T)0.5 * (z1.y + z2.y)};
@@ -457,20 +510,65 @@ __global__ void __launch_bounds__(1024) k_spread_fftx(const T4<T>* __restrict__ 
 // spectrum, inverse on the three field spectra).
 // Used forward on spec and inverse on the three field spectra.
 // ----------------------------------------------------------------------------
+// Final FP64 reduction of the z-pass partials with a fixed tree (bitwise
+// deterministic); run by block 0 of the inverse y pass, which follows the
+// z pass on the stream.
+__device__ void reduce_partials(const double* __restrict__ partials, int nblk, double pre,
+                                double* __restrict__ energy, double* __restrict__ virial, double* red) {
+  // red: 7 * blockDim.x doubles of LDS
+  const int t = threadIdx.x, nt = blockDim.x;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    double a = 0.0;
+    for (int b = t; b < nblk; b += nt) a += partials[(size_t)b * 8 + c];
+    red[c * nt + t] = a;
+  }
+  __syncthreads();
+  for (int h = nt >> 1; h > 0; h >>= 1) {
+    if (t < h) {
+#pragma unroll
+      for (int c = 0; c < 7; ++c) red[c * nt + t] += red[c * nt + t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) *energy = pre * red[0];
+  if (t >= 1 && t < 7 && virial) virial[t - 1] = pre * red[t * nt];
+}
+
 template <typename T, bool INV>
-__global__ void __launch_bounds__(1024) k_ffty(cpx<T>* __restrict__ data, const cpx<T>* __restrict__ twg, Geo g) {
+__global__ void __launch_bounds__(256) k_ffty(cpx<T>* __restrict__ data, const cpx<T>* __restrict__ twg, Geo g,
+                                              const double* __restrict__ partials, double pre,
+                                              double* __restrict__ energy, double* __restrict__ virial) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int Ky = g.K[1], Kz = g.K[2];
+  const int RS = padded_len(Ky) + 1;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);
-  cpx<T>* tw = buf + g.zb * Ky;
+  cpx<T>* tw = buf + g.zb * RS;
   const int nzb = Kz / g.zb;
   const int plane = blockIdx.x / nzb, zblk = blockIdx.x % nzb;
   cpx<T>* base = data + ((size_t)plane * Kz + (size_t)zblk * g.zb) * Ky;
-  for (int e = threadIdx.x; e < g.zb * Ky; e += blockDim.x) buf[e] = base[e];
-  for (int e = threadIdx.x; e < g.twN; e += blockDim.x) tw[e] = twg[e];
+  const int n = g.zb * Ky, lky = 31 - __clz(Ky);
+  for (int b0 = threadIdx.x; b0 < n; b0 += 16 * blockDim.x) {
+    cpx<T> r[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = b0 + u * blockDim.x;
+      if (e < n) r[u] = base[e];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = b0 + u * blockDim.x;
+      if (e < n) buf[(e >> lky) * RS + lds_pad(e & (Ky - 1))] = r[u];
+    }
+  }
+  copy_g2s<8>(tw, twg, g.twN);
   __syncthreads();
-  fft_rows<T, INV, kEPT>(buf, g.zb, Ky, Ky, 1, false, tw, g.twN);
-  for (int e = threadIdx.x; e < g.zb * Ky; e += blockDim.x) base[e] = buf[e];
+  fft_rows<T, INV, kEPT, true>(buf, g.zb, Ky, RS, 1, false, tw, g.twN);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) base[e] = buf[(e >> lky) * RS + lds_pad(e & (Ky - 1))];
+  if (INV && energy && blockIdx.x == 0) {
+    __syncthreads();
+    reduce_partials(partials, g.nzblk, pre, energy, virial, reinterpret_cast<double*>(smem));
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -497,11 +595,20 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
 
   const int nyb = Ky / yb;
   const int kx = blockIdx.x / nyb, y0 = (blockIdx.x % nyb) * yb;
-  for (int e = threadIdx.x; e < Kz * yb; e += blockDim.x) {
-    const int yl = e % yb, z = e / yb;
-    buf[z * w3 + yl] = spec[((size_t)kx * Kz + z) * Ky + y0 + yl];
+  for (int base = threadIdx.x; base < Kz * yb; base += 8 * blockDim.x) {
+    cpx<T> r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = base + u * blockDim.x;
+      if (e < Kz * yb) r[u] = spec[((size_t)kx * Kz + e / yb) * Ky + y0 + e % yb];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = base + u * blockDim.x;
+      if (e < Kz * yb) buf[(e / yb) * w3 + e % yb] = r[u];
+    }
   }
-  for (int e = threadIdx.x; e < g.twN; e += blockDim.x) tw[e] = twg[e];
+  copy_g2s<8>(tw, twg, g.twN);
   __syncthreads();
   fft_rows<T, false, kEPT>(buf, yb, Kz, 1, w3, true, tw, g.twN);
 
@@ -510,32 +617,45 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
   const double wgt = (kx == 0 || kx == Kx / 2) ? 1.0 : 2.0;
   const double kxv = pc.two_pi_over_L[0] * kx;
   const double kxd = (kx == Kx / 2) ? 0.0 : kxv;
-  for (int e = threadIdx.x; e < Kz * yb; e += blockDim.x) {
-    const int yl = e % yb, z = e / yb;
-    const int ny = y0 + yl;
-    const int ay = min(ny, Ky - ny), az = min(z, Kz - z);
-    const double kyv = pc.two_pi_over_L[1] * (ny <= Ky / 2 ? ny : ny - Ky);
-    const double kzv = pc.two_pi_over_L[2] * (z <= Kz / 2 ? z : z - Kz);
-    const double kyd = (2 * ny == Ky) ? 0.0 : kyv;
-    const double kzd = (2 * z == Kz) ? 0.0 : kzv;
-    const double Gv = G[((size_t)kx * Kyh + ay) * Kzh + az];
-    const cpx<T> q = buf[z * w3 + yl];
-    const double s2 = (double)q.x * (double)q.x + (double)q.y * (double)q.y;
-    const double t = wgt * Gv * s2;
-    const double k2 = kxv * kxv + kyv * kyv + kzv * kzv;
-    const double c = (k2 > 0.0) ? 2.0 * (1.0 + k2 * pc.inv_4beta2) / k2 : 0.0;
-    acc[0] += t;
-    acc[1] += t * (1.0 - c * kxv * kxv);
-    acc[2] += t * (1.0 - c * kyv * kyv);
-    acc[3] += t * (1.0 - c * kzv * kzv);
-    acc[4] += t * (-c * kxd * kyd);
-    acc[5] += t * (-c * kxd * kzd);
-    acc[6] += t * (-c * kyd * kzd);
-    // -i k' G Q^ = k' G (q.y, -q.x)
-    const T gx = (T)(Gv * kxd), gy = (T)(Gv * kyd), gz = (T)(Gv * kzd);
-    buf[z * w3 + yl] = cpx<T>{gx * q.y, -gx * q.x};
-    buf[z * w3 + yb + yl] = cpx<T>{gy * q.y, -gy * q.x};
-    buf[z * w3 + 2 * yb + yl] = cpx<T>{gz * q.y, -gz * q.x};
+  for (int base = threadIdx.x; base < Kz * yb; base += 8 * blockDim.x) {
+    double Gr[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = base + u * blockDim.x;
+      if (e < Kz * yb) {
+        const int yl = e % yb, z = e / yb, ny = y0 + yl;
+        Gr[u] = G[((size_t)kx * Kyh + min(ny, Ky - ny)) * Kzh + min(z, Kz - z)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = base + u * blockDim.x;
+      if (e >= Kz * yb) continue;
+      const int yl = e % yb, z = e / yb;
+      const int ny = y0 + yl;
+      const double kyv = pc.two_pi_over_L[1] * (ny <= Ky / 2 ? ny : ny - Ky);
+      const double kzv = pc.two_pi_over_L[2] * (z <= Kz / 2 ? z : z - Kz);
+      const double kyd = (2 * ny == Ky) ? 0.0 : kyv;
+      const double kzd = (2 * z == Kz) ? 0.0 : kzv;
+      const double Gv = Gr[u];
+      const cpx<T> q = buf[z * w3 + yl];
+      const double s2 = (double)q.x * (double)q.x + (double)q.y * (double)q.y;
+      const double t = wgt * Gv * s2;
+      const double k2 = kxv * kxv + kyv * kyv + kzv * kzv;
+      const double c = (k2 > 0.0) ? 2.0 * (1.0 + k2 * pc.inv_4beta2) / k2 : 0.0;
+      acc[0] += t;
+      acc[1] += t * (1.0 - c * kxv * kxv);
+      acc[2] += t * (1.0 - c * kyv * kyv);
+      acc[3] += t * (1.0 - c * kzv * kzv);
+      acc[4] += t * (-c * kxd * kyd);
+      acc[5] += t * (-c * kxd * kzd);
+      acc[6] += t * (-c * kyd * kzd);
+      // -i k' G Q^ = k' G (q.y, -q.x)
+      const T gx = (T)(Gv * kxd), gy = (T)(Gv * kyd), gz = (T)(Gv * kzd);
+      buf[z * w3 + yl] = cpx<T>{gx * q.y, -gx * q.x};
+      buf[z * w3 + yb + yl] = cpx<T>{gy * q.y, -gy * q.x};
+      buf[z * w3 + 2 * yb + yl] = cpx<T>{gz * q.y, -gz * q.x};
+    }
   }
   __syncthreads();
   fft_rows<T, true, kEPT>(buf, w3, Kz, 1, w3, true, tw, g.twN);
@@ -563,113 +683,157 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
 }
 
 // ----------------------------------------------------------------------------
-// Final FP64 reduction of the z-pass partials (fixed tree: deterministic).
+// Inverse complex-to-real transform along x of the three field spectra.  A
+// workgroup takes one z plane and yb consecutive y rows of all three fields
+// (3 * yb real rows, transformed in pairs as complex rows) and writes the
+// real fields interleaved, E[z][y][x] = (Ex, Ey, Ez), so the gather reads one
+// 3-component record per stencil point.
 // ----------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partials, int nblk, double pre,
-                                                double* __restrict__ energy, double* __restrict__ virial) {
-  __shared__ double red[7][256];
-  const int t = threadIdx.x;
+template <typename T>
+struct F3 {
+  T x, y, z;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_ifftx(const cpx<T>* __restrict__ fspec, F3<T>* __restrict__ field,
+                                               const cpx<T>* __restrict__ twg, Geo g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2], Kh = g.Kh;
+  const int yb = g.xyb;                  // y rows per block
+  const int nrc = (3 * yb) / 2;          // complex rows: pair (2c, 2c+1) of rows r = a*yb + yl
+  const int RS = padded_len(Kx) + 1;
+  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem);  // [nrc][RS]
+  cpx<T>* tw = tile + (size_t)nrc * RS;
+  const int nyb = Ky / yb;
+  const int z = blockIdx.x / nyb, y0 = (blockIdx.x % nyb) * yb;
+  const size_t fstride = (size_t)Kh * Kz * Ky, plane = (size_t)Kz * Ky;
+  copy_g2s<8>(tw, twg, g.twN);
+
+  // load: thread -> (pair c, kx = k0, k0 + kstep, ...)
+  const int c_t = threadIdx.x % nrc, k_t = threadIdx.x / nrc, kstep = blockDim.x / nrc;
+  if (k_t < kstep) {
+    const int r0 = 2 * c_t, r1 = r0 + 1;
+    const cpx<T>* s0 = fspec + (size_t)(r0 / yb) * fstride + (size_t)z * Ky + y0 + r0 % yb;
+    const cpx<T>* s1 = fspec + (size_t)(r1 / yb) * fstride + (size_t)z * Ky + y0 + r1 % yb;
+    cpx<T>* zr = tile + (size_t)c_t * RS;
+    for (int kb = k_t; kb < Kh; kb += 4 * kstep) {
+      cpx<T> A[4], B[4];
 #pragma unroll
-  for (int c = 0; c < 7; ++c) {
-    double a = 0.0;
-    for (int b = t; b < nblk; b += 256) a += partials[(size_t)b * 8 + c];
-    red[c][t] = a;
+      for (int u = 0; u < 4; ++u) {
+        const int kk = kb + u * kstep;
+        if (kk < Kh) { A[u] = s0[(size_t)kk * plane]; B[u] = s1[(size_t)kk * plane]; }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = kb + u * kstep;
+        if (kk < Kh) {
+          cpx<T> av = A[u], bv = B[u];
+          if (kk == 0 || kk == Kx / 2) { av.y = (T)0; bv.y = (T)0; }
+          zr[lds_pad(kk)] = cpx<T>{av.x - bv.y, av.y + bv.x};
+          if (kk > 0 && kk < Kx / 2) zr[lds_pad(Kx - kk)] = cpx<T>{av.x + bv.y, bv.x - av.y};
+        }
+      }
+    }
   }
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (t < h) {
+  fft_rows<T, true, kEPT, true>(tile, nrc, Kx, RS, 1, false, tw, g.twN);
+
+  // store: record (yl, x) gathers component a from row r = a*yb + yl
+  const T* tr = reinterpret_cast<const T*>(tile);
+  F3<T>* out = field + ((size_t)z * Ky + y0) * Kx;
+  const int lkx = 31 - __clz(Kx);
+  for (int e = threadIdx.x; e < yb * Kx; e += blockDim.x) {
+    const int yl = e >> lkx, x = e & (Kx - 1);
+    const int col = 2 * lds_pad(x);
+    T v[3];
 #pragma unroll
-      for (int c = 0; c < 7; ++c) red[c][t] += red[c][t + h];
+    for (int a = 0; a < 3; ++a) {
+      const int r = a * yb + yl;
+      v[a] = tr[2 * (size_t)(r >> 1) * RS + col + (r & 1)];
     }
-    __syncthreads();
+    out[e] = F3<T>{v[0], v[1], v[2]};
   }
-  if (t == 0) *energy = pre * red[0][0];
-  if (t >= 1 && t < 7 && virial) virial[t - 1] = pre * red[t][0];
 }
 
 // ----------------------------------------------------------------------------
-// Inverse complex-to-real transform along x of the field
-// rows a pencil's particles need, then force interpolation with the same
-// assignment weights as the spread.  One workgroup owns the particles whose
-// stencil starts in rows y in [y0, y0+gcy), z in [z0, z0+gcz); it loads rows
-// [y0, y0+gcy+p-1) x [z0, z0+gcz+p-1) (mod K) of one field at a time, so each
-// force component is written exactly once by one thread.
+// Force interpolation with the assignment weights of the spread, reading the
+// real fields from memory (L1/L2).  P lanes serve one particle: lane tx reads
+// the column s_x + tx of all P x P (y, z) rows, so each group's loads cover
+// P consecutive records; the P partial sums are then added across the group.
+// Blocks walk the sorted particles in order, and consecutive chunks are
+// mapped to the same XCD so each XCD's L2 serves one slab of the field.
 // ----------------------------------------------------------------------------
 template <typename T, int P>
-__global__ void __launch_bounds__(1024) k_ifftx_gather(const cpx<T>* __restrict__ fspec, const T4<T>* __restrict__ sorted,
-                                                       const int* __restrict__ sidx, const int* __restrict__ perm, const int* __restrict__ bin_start,
-                                                       T* __restrict__ ion_f, T* __restrict__ wc_f, int64_t n_ion,
-                                                       T fscale, int accumulate, const cpx<T>* __restrict__ twg, Geo g) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2], Kh = g.Kh;
-  const int RY = g.gcy + P - 1, RZ = g.gcz + P - 1;
-  const int nrows = RY * RZ, nrc = (nrows + 1) >> 1;
-  cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem);
-  cpx<T>* tw = tile + nrc * Kx;
-  __shared__ Ranges R;
-
-  const int py = blockIdx.x % g.gpy, pz = blockIdx.x / g.gpy;
-  const int y0 = py * g.gcy, z0 = pz * g.gcz;
-  for (int e = threadIdx.x; e < g.twN; e += blockDim.x) tw[e] = twg[e];
-  if (threadIdx.x == 0) build_ranges(R, bin_start, g, z0, g.gcz, y0 >> 2, g.gcy >> 2);
-  __syncthreads();
-  const int total = R.pre[R.n];
-  const T* tile_r = reinterpret_cast<const T*>(tile);
-
+__global__ void __launch_bounds__(256) k_gather(const F3<T>* __restrict__ field, const T4<T>* __restrict__ sorted,
+                                                const int* __restrict__ sidx, const int* __restrict__ perm,
+                                                int n, int nchunks, T* __restrict__ ion_f, T* __restrict__ wc_f,
+                                                int64_t n_ion, T fscale, int accumulate, int nxcd, Geo g) {
+  const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2];
+  constexpr int GPW = 64 / P;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / P, tx = lane - grp * P;
+  const bool lane_on = grp < GPW;
+  const int per_block = (blockDim.x >> 6) * GPW;
+  // XCD-aware order: blocks b, b + nxcd, ... run on one XCD; give them
+  // consecutive chunks of the sorted particles.  The grid is a multiple of
+  // nxcd, so b -> chunk is a bijection onto [0, gridDim.x); chunks at or
+  // beyond nchunks hold no particles.
+  const int per_xcd = gridDim.x / nxcd;
+  const int chunk = (blockIdx.x % nxcd) * per_xcd + blockIdx.x / nxcd;
+  const int v = chunk * per_block + wave * GPW + grp;
+  const bool on = lane_on && chunk < nchunks && v < n;
+  T part[3] = {(T)0, (T)0, (T)0};
+  T qw = (T)0;
+  int src = 0;
+  if (on) {
+    const T4<T> pt = sorted[v];
+    const int sp = sidx[v];
+    src = perm[v];
+    const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
+    T wx[P], wy[P], wz[P];
+    bspline_weights<T, P>(pt.x, wx);
+    bspline_weights<T, P>(pt.y, wy);
+    bspline_weights<T, P>(pt.z, wz);
+    T wxt = wx[0];
+#pragma unroll
+    for (int q = 1; q < P; ++q) wxt = (tx == q) ? wx[q] : wxt;
+    int gx = sx + tx;
+    if (gx >= Kx) gx -= Kx;
+#pragma unroll
+    for (int tz = 0; tz < P; ++tz) {
+      int gz = sz + tz;
+      if (gz >= Kz) gz -= Kz;
+      F3<T> r[P];
+#pragma unroll
+      for (int ty = 0; ty < P; ++ty) {
+        int gy = sy + ty;
+        if (gy >= Ky) gy -= Ky;
+        r[ty] = field[((size_t)gz * Ky + gy) * Kx + gx];
+      }
+#pragma unroll
+      for (int ty = 0; ty < P; ++ty) {
+        const T w = wz[tz] * wy[ty];
+        part[0] += w * r[ty].x;
+        part[1] += w * r[ty].y;
+        part[2] += w * r[ty].z;
+      }
+    }
+    qw = fscale * pt.w * wxt;
+  }
+  const int gbase = grp * P;
+  T tot[3];
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const cpx<T>* fs = fspec + (size_t)a * Kh * Kz * Ky;
-    for (int e = threadIdx.x; e < nrc * Kh; e += blockDim.x) {
-      const int cr = e % nrc, k = e / nrc;
-      const int r0 = 2 * cr, r1 = 2 * cr + 1;
-      const int gy0 = wrapi(y0 + r0 % RY, Ky), gz0 = wrapi(z0 + r0 / RY, Kz);
-      cpx<T> A = fs[((size_t)k * Kz + gz0) * Ky + gy0];
-      cpx<T> B = {(T)0, (T)0};
-      if (r1 < nrows) {
-        const int gy1 = wrapi(y0 + r1 % RY, Ky), gz1 = wrapi(z0 + r1 / RY, Kz);
-        B = fs[((size_t)k * Kz + gz1) * Ky + gy1];
-      }
-      if (k == 0 || k == Kx / 2) { A.y = (T)0; B.y = (T)0; }
-      cpx<T>* zr = tile + cr * Kx;
-      zr[k] = cpx<T>{A.x - B.y, A.y + B.x};
-      if (k > 0 && k < Kx / 2) zr[Kx - k] = cpx<T>{A.x + B.y, B.x - A.y};
-    }
-    __syncthreads();
-    fft_rows<T, true, kEPT>(tile, nrc, Kx, Kx, 1, false, tw, g.twN);
-
-    for (int v = threadIdx.x; v < total; v += blockDim.x) {
-      const int idx = range_index(R, v);
-      const T4<T> pt = sorted[idx];
-      const int sp = sidx[idx];
-      const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
-      T wx[P], wy[P], wz[P];
-      bspline_weights<T, P>(pt.x, wx);
-      bspline_weights<T, P>(pt.y, wy);
-      bspline_weights<T, P>(pt.z, wz);
-      T acc = (T)0;
+    const T mine = qw * part[a];
+    T s = (T)0;
 #pragma unroll
-      for (int tz = 0; tz < P; ++tz) {
-        T sy_acc = (T)0;
+    for (int q = 0; q < P; ++q) s += __shfl(mine, gbase + q, 64);
+    tot[a] = s;
+  }
+  if (on && tx == 0) {
+    T* out = (src < n_ion) ? (ion_f + 3 * (int64_t)src) : (wc_f + 3 * ((int64_t)src - n_ion));
 #pragma unroll
-        for (int ty = 0; ty < P; ++ty) {
-          const int row = (sz - z0 + tz) * RY + (sy - y0 + ty);
-          const T* rp = tile_r + 2 * (row >> 1) * Kx + (row & 1);
-          T sx_acc = (T)0;
-#pragma unroll
-          for (int tx = 0; tx < P; ++tx) {
-            int gx = sx + tx;
-            if (gx >= Kx) gx -= Kx;
-            sx_acc += wx[tx] * rp[2 * gx];
-          }
-          sy_acc += wy[ty] * sx_acc;
-        }
-        acc += wz[tz] * sy_acc;
-      }
-      const T f = fscale * pt.w * acc;
-      const int src = perm[idx];
-      T* out = (src < n_ion) ? (ion_f + 3 * (int64_t)src) : (wc_f + 3 * ((int64_t)src - n_ion));
-      out[a] = accumulate ? out[a] + f : f;
-    }
-    __syncthreads();
+    for (int a = 0; a < 3; ++a) out[a] = accumulate ? out[a] + tot[a] : tot[a];
   }
 }
 
