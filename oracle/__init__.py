@@ -8,4 +8,6 @@ does, and shares no code with this package.
               real-space and self terms for the Madelung check)
   ewald_np  - NumPy twin of the reciprocal sum for small systems
   pppm      - FP64 NumPy PPPM with ik-differentiation (full spectra)
+  learned   - FP64 NumPy descriptor, MLP, force head, manual backprop and Adam
+              of the learned coarse-mesh correction
 """
