@@ -167,6 +167,93 @@ dplr_lr_status dplr_lr_profile_read(dplr_lr_plan p, double* ms, int64_t* calls, 
                                     int32_t reset);
 const char* dplr_lr_profile_stage_name(int32_t i);
 
+/* ------------------------------------------------------------------------
+ * Learned coarse-mesh correction.  A plan on a mesh twice as coarse computes
+ * PPPM forces; this network adds a per-particle correction dF_i predicted from
+ * the particle's charge neighbourhood, trained on fine-minus-coarse PPPM force
+ * residuals the method itself generates.  The structure follows the paper's
+ * Deep Potential / Deep Wannier description (DPLR background section):
+ * a descriptor D_i built from the neighbour list, then a three-hidden-layer
+ * fitting net, here predicting a vector per particle as the Deep Wannier
+ * model does.  Definitions:
+ *   T_i[k, a] = sum_{j: r_ij < cutoff} q_j T_k(2 r_ij / cutoff - 1) s(r_ij) u_a,
+ *     T_k Chebyshev (k < 32), s(r) = (1 + cos(pi r / cutoff)) / 2,
+ *     u = (1, unit vector from i to j);
+ *   D_i[4k + l] = sum_a T_i[k, a] T_i[l, a] (l < 4); x_i = (D_i - mu) * inv_sigma;
+ *   h1 = silu(x W1 + b1), h2 = silu(h1 W2 + b2), h3 = silu(h2 W3 + b3),
+ *   c = h3 W4 + b4 (128 -> 64 -> 64 -> 64 -> 32; BF16 MFMA, FP32 accumulate);
+ *   dF_i = out_scale * q_i * sum_k c_ik T_i[k, 1:4].
+ * Packed FP32 parameters: W1[128][64] b1[64] W2[64][64] b2[64] W3[64][64]
+ * b3[64] W4[64][32] b4[32] mu[128] inv_sigma[128] (W stored [in][out]).
+ * Positions, charges, forces and targets are FP32 device arrays [n][3] / [n];
+ * the box is orthorhombic (host double[3]) and at least 3 cutoffs long.
+ * ---------------------------------------------------------------------- */
+typedef struct dplr_lr_mlp_s* dplr_lr_mlp;
+
+typedef struct {
+  double cutoff;     /* neighbour cutoff (A), default 4 */
+  double out_scale;  /* fixed output scale of the force head, default 0.01 */
+  int64_t capacity;  /* maximum n_ion + n_wc */
+  uint32_t flags;    /* reserved, 0 */
+} dplr_lr_mlp_config;
+
+void dplr_lr_mlp_config_default(dplr_lr_mlp_config* cfg);
+int64_t dplr_lr_mlp_param_count(void);
+/* Allocates the network's workspace for `capacity` particles; parameters start at zero. */
+dplr_lr_status dplr_lr_mlp_create(const dplr_lr_mlp_config* cfg, void* hip_stream, dplr_lr_mlp* out);
+dplr_lr_status dplr_lr_mlp_destroy(dplr_lr_mlp m);
+dplr_lr_status dplr_lr_mlp_set_stream(dplr_lr_mlp m, void* hip_stream);
+/* Host copies of the packed parameters (synchronous); set_params resets the Adam state. */
+dplr_lr_status dplr_lr_mlp_set_params(dplr_lr_mlp m, const float* host_params, int64_t count);
+dplr_lr_status dplr_lr_mlp_get_params(dplr_lr_mlp m, float* host_params, int64_t count);
+/* dF for every particle, written (accumulate = 0) or added (accumulate != 0)
+ * to ion_dF / wc_dF.  The first call for a larger box grows the cell list
+ * (device allocation); later calls allocate nothing. */
+dplr_lr_status dplr_lr_mlp_forward(dplr_lr_mlp m, const double box[3], int64_t n_ion, const float* ion_pos,
+                                   const float* ion_q, int64_t n_wc, const float* wc_pos, const float* wc_q,
+                                   float* ion_dF, float* wc_dF, int32_t accumulate);
+/* One training step on the mean-squared error between dF and the targets:
+ * forward, backward (BF16 MFMA, FP32 accumulate), deterministic gradient sum
+ * and, when lr > 0, an Adam update (beta 0.9 / 0.999, eps 1e-8).  *loss
+ * (device double) receives the loss before the update; grad_out (device
+ * float[count of trainable parameters], may be NULL) the gradient. */
+dplr_lr_status dplr_lr_mlp_train_step(dplr_lr_mlp m, const double box[3], int64_t n_ion, const float* ion_pos,
+                                      const float* ion_q, int64_t n_wc, const float* wc_pos, const float* wc_q,
+                                      const float* ion_target, const float* wc_target, float lr, double* loss,
+                                      float* grad_out);
+/* The descriptor T (device float [n][128], index 4k + a) in the network's
+ * cell order, and that order (device int [n], original particle indices;
+ * ions first).  Either output may be NULL. */
+dplr_lr_status dplr_lr_mlp_descriptor(dplr_lr_mlp m, const double box[3], int64_t n_ion, const float* ion_pos,
+                                      const float* ion_q, int64_t n_wc, const float* wc_pos, const float* wc_q,
+                                      float* T_sorted, int32_t* order);
+const char* dplr_lr_mlp_last_error(dplr_lr_mlp m);
+
+/* Fallback guard (host only).  The learned form is used only while the
+ * inputs look like the training data and periodic audits (a fine-mesh
+ * recomputation compared with the learned result) stay within tolerance;
+ * otherwise the caller runs the fine plan. */
+#define DPLR_LR_GUARD_LEARNED 0
+#define DPLR_LR_GUARD_FINE 1
+#define DPLR_LR_GUARD_AUDIT 2
+typedef struct {
+  double max_audit_rel_rmse;    /* relative force RMSE allowed at an audit            */
+  double max_correction_ratio;  /* max |dF| allowed as a fraction of max |F| (0: off)  */
+  int64_t audit_interval;       /* steps between audits (0: only the first)          */
+  double min_neighbours, max_neighbours;  /* neighbour-count range seen in training (0: off) */
+} dplr_lr_guard_config;
+typedef struct {
+  int32_t audit_valid;          /* an audit has been taken                           */
+  double audit_rel_rmse;        /* its relative force RMSE                           */
+  int64_t steps_since_audit;
+  double max_correction, max_force;
+  double min_neighbours, max_neighbours;
+  int32_t unseen_charges;       /* particles whose charge was absent from training   */
+} dplr_lr_guard_stats;
+/* *decision = DPLR_LR_GUARD_LEARNED, _FINE or _AUDIT (run both and compare). */
+dplr_lr_status dplr_lr_guard_decide(const dplr_lr_guard_config* cfg, const dplr_lr_guard_stats* stats,
+                                    int32_t* decision);
+
 #ifdef __cplusplus
 }
 #endif

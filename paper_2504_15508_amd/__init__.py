@@ -6,5 +6,6 @@ from . import _lib
 from ._lib import DplrError
 from .plan import Plan
 from .autograd import DPLRLongRange, dplr_long_range
+from .learned import Mlp, LearnedCoarse, train as train_correction
 
-__all__ = ["Plan", "DPLRLongRange", "dplr_long_range", "DplrError"]
+__all__ = ["Plan", "DPLRLongRange", "dplr_long_range", "DplrError", "Mlp", "LearnedCoarse", "train_correction"]

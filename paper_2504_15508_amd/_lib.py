@@ -24,7 +24,29 @@ EXPORTS = [
     "dplr_lr_compute_energy_forces_virial", "dplr_lr_scale_grad", "dplr_lr_plan_destroy",
     "dplr_lr_last_error", "dplr_lr_workspace_bytes", "dplr_lr_debug_copy", "dplr_lr_debug_size",
     "dplr_lr_profile_enable", "dplr_lr_profile_read", "dplr_lr_profile_stage_name",
+    "dplr_lr_mlp_config_default", "dplr_lr_mlp_param_count", "dplr_lr_mlp_create", "dplr_lr_mlp_destroy",
+    "dplr_lr_mlp_set_stream", "dplr_lr_mlp_set_params", "dplr_lr_mlp_get_params", "dplr_lr_mlp_forward",
+    "dplr_lr_mlp_train_step", "dplr_lr_mlp_descriptor", "dplr_lr_mlp_last_error", "dplr_lr_guard_decide",
 ]
+GUARD_LEARNED, GUARD_FINE, GUARD_AUDIT = 0, 1, 2
+
+
+class MlpConfig(ctypes.Structure):
+    _fields_ = [("cutoff", ctypes.c_double), ("out_scale", ctypes.c_double), ("capacity", ctypes.c_int64),
+                ("flags", ctypes.c_uint32)]
+
+
+class GuardConfig(ctypes.Structure):
+    _fields_ = [("max_audit_rel_rmse", ctypes.c_double), ("max_correction_ratio", ctypes.c_double),
+                ("audit_interval", ctypes.c_int64), ("min_neighbours", ctypes.c_double),
+                ("max_neighbours", ctypes.c_double)]
+
+
+class GuardStats(ctypes.Structure):
+    _fields_ = [("audit_valid", ctypes.c_int32), ("audit_rel_rmse", ctypes.c_double),
+                ("steps_since_audit", ctypes.c_int64), ("max_correction", ctypes.c_double),
+                ("max_force", ctypes.c_double), ("min_neighbours", ctypes.c_double),
+                ("max_neighbours", ctypes.c_double), ("unseen_charges", ctypes.c_int32)]
 
 
 class Config(ctypes.Structure):
@@ -69,6 +91,20 @@ def load():
         "dplr_lr_profile_enable": ([p, i32], ctypes.c_int),
         "dplr_lr_profile_read": ([p, p, p, i32, p, i32], ctypes.c_int),
         "dplr_lr_profile_stage_name": ([i32], ctypes.c_char_p),
+        "dplr_lr_mlp_config_default": ([ctypes.POINTER(MlpConfig)], None),
+        "dplr_lr_mlp_param_count": ([], i64),
+        "dplr_lr_mlp_create": ([ctypes.POINTER(MlpConfig), p, ctypes.POINTER(p)], ctypes.c_int),
+        "dplr_lr_mlp_destroy": ([p], ctypes.c_int),
+        "dplr_lr_mlp_set_stream": ([p, p], ctypes.c_int),
+        "dplr_lr_mlp_set_params": ([p, p, i64], ctypes.c_int),
+        "dplr_lr_mlp_get_params": ([p, p, i64], ctypes.c_int),
+        "dplr_lr_mlp_forward": ([p, ctypes.POINTER(d), i64, p, p, i64, p, p, p, p, i32], ctypes.c_int),
+        "dplr_lr_mlp_train_step": ([p, ctypes.POINTER(d), i64, p, p, i64, p, p, p, p, ctypes.c_float, p, p],
+                                   ctypes.c_int),
+        "dplr_lr_mlp_descriptor": ([p, ctypes.POINTER(d), i64, p, p, i64, p, p, p, p], ctypes.c_int),
+        "dplr_lr_mlp_last_error": ([p], ctypes.c_char_p),
+        "dplr_lr_guard_decide": ([ctypes.POINTER(GuardConfig), ctypes.POINTER(GuardStats), ctypes.POINTER(i32)],
+                                 ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -81,4 +117,10 @@ def load():
 def check(status: int, plan_handle=None):
     if status != OK:
         msg = load().dplr_lr_last_error(plan_handle)
+        raise DplrError(status, msg.decode() if msg else "")
+
+
+def check_mlp(status: int, handle=None):
+    if status != OK:
+        msg = load().dplr_lr_mlp_last_error(handle)
         raise DplrError(status, msg.decode() if msg else "")

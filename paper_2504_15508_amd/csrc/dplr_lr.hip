@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -634,3 +635,5 @@ dplr_lr_status dplr_lr_debug_copy(dplr_lr_plan p, int32_t which, void* dst, int6
 }
 
 }  // extern "C"
+
+#include "learned_api.inc"

@@ -1,0 +1,466 @@
+// Learned coarse-mesh correction: neighbour descriptor, a 128-64-64-64-32
+// SiLU MLP on BF16 MFMA with FP32 accumulation, the equivariant force head,
+// and training (loss, backward, Adam) - all as gfx950 kernels.
+//
+//   T_i[k, a] = sum_{j: r_ij < rc} q_j T_k(2 r_ij / rc - 1) s(r_ij) u_a(i -> j),
+//               u = (1, unit vector), s(r) = (1 + cos(pi r / rc)) / 2, k < 32;
+//   D_i[4k + l] = sum_a T_i[k, a] T_i[l, a] (l < 4);  x_i = (D_i - mu) * inv_sigma;
+//   h1 = silu(x W1 + b1), h2 = silu(h1 W2 + b2), h3 = silu(h2 W3 + b3),
+//   c = h3 W4 + b4;  dF_i = s_out q_i sum_k c_ik T_i[k, 1:4].
+//
+// Packed parameter vector (FP32 master copy, the layout of the C ABI):
+//   W1[128][64] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[64][32] b4[32]
+//   mu[128] inv_sigma[128]                                   (18912 floats)
+#pragma once
+
+#include "pppm_kernels.hpp"
+
+namespace dplr {
+namespace mlp {
+
+constexpr int kIn = 128, kH = 64, kOut = 32;
+constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kIn * kH;
+constexpr int kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH;
+constexpr int kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kH * kH;
+constexpr int kOffW4 = kOffB3 + kH, kOffB4 = kOffW4 + kH * kOut;
+constexpr int kNTrain = kOffB4 + kOut;                // trainable parameters
+constexpr int kOffMu = kNTrain, kOffIsd = kOffMu + kIn;
+constexpr int kNParams = kOffIsd + kIn;               // packed total
+constexpr int kNWeights = kIn * kH + 2 * kH * kH + kH * kOut;  // bf16 weight copy
+constexpr int kRows = 128;                            // particles per MLP block (4 waves x 32)
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  // round to nearest even
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// acc (32 x 32) += A (32 x K) * B (K x 32) on one wave with
+// v_mfma_f32_32x32x8_bf16_1k.  Operands are bf16 in LDS addressed as
+// A(m, k) = A[m * sam + k * sak] and B(k, n) = B[k * sbk + n * sbn].
+// Lane l supplies A(l % 32, 4 (l / 32) + i) and B(4 (l / 32) + i, l % 32).
+__device__ __forceinline__ void mfma_tile(f32x16& acc, const unsigned short* A, int sam, int sak,
+                                          const unsigned short* B, int sbk, int sbn, int K) {
+  const int l = threadIdx.x & 63;
+  const int mn = l & 31, kh = (l >> 5) * 4;
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    bf16x4 a, b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = (short)A[mn * sam + (k0 + kh + i) * sak];
+      b[i] = (short)B[(k0 + kh + i) * sbk + mn * sbn];
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+  }
+}
+
+// row / column of accumulator register r of this lane in the 32 x 32 tile
+__device__ __forceinline__ int acc_row(int r) { return 8 * (r >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (r & 3); }
+__device__ __forceinline__ int acc_col() { return threadIdx.x & 31; }
+
+__device__ __forceinline__ void zero(f32x16& a) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) a[r] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Cell list: cells of edge >= rc per axis (at least 3 per axis).
+// ---------------------------------------------------------------------------
+struct CellGeo {
+  int nc[3];
+  float L[3], invL[3], cinv[3];  // box, 1/box, cells per Angstrom
+  float rc;
+  int ncells;
+};
+
+__device__ __forceinline__ float wrapf(float v, float L, float invL) {
+  v -= L * floorf(v * invL);
+  if (v >= L) v -= L;
+  if (!(v >= 0.0f && v < L)) v = 0.0f;
+  return v;
+}
+
+__device__ __forceinline__ int cell_of(float x, float y, float z, const CellGeo& c) {
+  int cx = min((int)(x * c.cinv[0]), c.nc[0] - 1);
+  int cy = min((int)(y * c.cinv[1]), c.nc[1] - 1);
+  int cz = min((int)(z * c.cinv[2]), c.nc[2] - 1);
+  return (cz * c.nc[1] + cy) * c.nc[0] + cx;
+}
+
+__global__ void k_cell_count(const float* __restrict__ ion_pos, const float* __restrict__ wc_pos, int64_t n_ion,
+                             int64_t n, int* __restrict__ count, CellGeo c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* r = (i < n_ion) ? ion_pos + 3 * i : wc_pos + 3 * (i - n_ion);
+  const float x = wrapf(r[0], c.L[0], c.invL[0]), y = wrapf(r[1], c.L[1], c.invL[1]),
+              z = wrapf(r[2], c.L[2], c.invL[2]);
+  atomicAdd(count + cell_of(x, y, z, c), 1);
+}
+
+__global__ void k_cell_scatter(const float* __restrict__ ion_pos, const float* __restrict__ wc_pos,
+                               const float* __restrict__ ion_q, const float* __restrict__ wc_q, int64_t n_ion,
+                               int64_t n, int* __restrict__ cursor, float4* __restrict__ cpos,
+                               int* __restrict__ cidx, CellGeo c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* r = (i < n_ion) ? ion_pos + 3 * i : wc_pos + 3 * (i - n_ion);
+  const float x = wrapf(r[0], c.L[0], c.invL[0]), y = wrapf(r[1], c.L[1], c.invL[1]),
+              z = wrapf(r[2], c.L[2], c.invL[2]);
+  const float q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
+  const int slot = atomicAdd(cursor + cell_of(x, y, z, c), 1);
+  cpos[slot] = make_float4(x, y, z, q);
+  cidx[slot] = (int)i;
+}
+
+// ---------------------------------------------------------------------------
+// Descriptor: one thread per (cell-sorted) particle.  Writes T [n][128] (FP32,
+// index 4k + a) and the normalised MLP input x [n][128] (bf16).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(128) k_descriptor(const float4* __restrict__ cpos, const int* __restrict__ start,
+                                                    int n, const float* __restrict__ params,
+                                                    float* __restrict__ Tout, unsigned short* __restrict__ X,
+                                                    CellGeo c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 pi = cpos[i];
+  float T[32][4];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) T[k][a] = 0.0f;
+  }
+  const int cx = min((int)(pi.x * c.cinv[0]), c.nc[0] - 1);
+  const int cy = min((int)(pi.y * c.cinv[1]), c.nc[1] - 1);
+  const int cz = min((int)(pi.z * c.cinv[2]), c.nc[2] - 1);
+  const float rc2 = c.rc * c.rc, inv_rc = 1.0f / c.rc;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int zz = (cz + dz + c.nc[2]) % c.nc[2];
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = (cy + dy + c.nc[1]) % c.nc[1];
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xx = (cx + dx + c.nc[0]) % c.nc[0];
+        const int cell = (zz * c.nc[1] + yy) * c.nc[0] + xx;
+        const int j1 = start[cell + 1];
+        for (int j = start[cell]; j < j1; ++j) {
+          if (j == i) continue;
+          const float4 pj = cpos[j];
+          float d0 = pj.x - pi.x, d1 = pj.y - pi.y, d2 = pj.z - pi.z;
+          d0 -= c.L[0] * rintf(d0 * c.invL[0]);
+          d1 -= c.L[1] * rintf(d1 * c.invL[1]);
+          d2 -= c.L[2] * rintf(d2 * c.invL[2]);
+          const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
+          if (r2 >= rc2 || r2 == 0.0f) continue;
+          const float r = sqrtf(r2), ir = 1.0f / r;
+          const float s = 0.5f * (1.0f + __cosf(3.14159265358979f * r * inv_rc));
+          const float xk = 2.0f * r * inv_rc - 1.0f;
+          const float w = pj.w * s;
+          const float u1 = d0 * ir, u2 = d1 * ir, u3 = d2 * ir;
+          float tm = 1.0f, t = xk;  // T_0, T_1
+#pragma unroll
+          for (int k = 0; k < 32; ++k) {
+            float g;
+            if (k == 0) g = 1.0f;
+            else if (k == 1) g = xk;
+            else { const float tn = 2.0f * xk * t - tm; tm = t; t = tn; g = tn; }
+            const float wg = w * g;
+            T[k][0] += wg;
+            T[k][1] += wg * u1;
+            T[k][2] += wg * u2;
+            T[k][3] += wg * u3;
+          }
+        }
+      }
+    }
+  }
+  float* to = Tout + (size_t)i * 128;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    reinterpret_cast<float4*>(to)[k] = make_float4(T[k][0], T[k][1], T[k][2], T[k][3]);
+  }
+  const float* mu = params + kOffMu;
+  const float* isd = params + kOffIsd;
+  unsigned short* xo = X + (size_t)i * 128;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const float d = T[k][0] * T[l][0] + T[k][1] * T[l][1] + T[k][2] * T[l][2] + T[k][3] * T[l][3];
+      const int f = 4 * k + l;
+      xo[f] = f2bf((d - mu[f]) * isd[f]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MLP forward + force head.  Block = 4 waves = 128 particles, wave w owns
+// rows 32w..32w+31.  Weights (bf16, transposed: Wt[out][in]) and biases are
+// staged in LDS; activations go layer to layer through LDS.  In training
+// mode the pre-activations z1..z3 and activations h1..h3 are stored, and the
+// head also forms the loss and dL/dc.
+// ---------------------------------------------------------------------------
+struct FwdLds {
+  unsigned short wt[kNWeights];   // W1t [64][128], W2t [64][64], W3t [64][64], W4t [32][64]
+  float b[kH * 3 + kOut];
+  unsigned short x[kRows][kIn];
+  unsigned short h[2][kRows][kH];
+  float c[kRows][kOut];
+  double lred[4];
+};
+
+template <bool TRAIN>
+__global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restrict__ X, const float* __restrict__ Tin,
+                                                 const float4* __restrict__ cpos, const int* __restrict__ cidx,
+                                                 int n, int64_t n_ion, const unsigned short* __restrict__ wt_g,
+                                                 const float* __restrict__ params, float s_out,
+                                                 float* __restrict__ ion_dF, float* __restrict__ wc_dF,
+                                                 int accumulate,
+                                                 // training
+                                                 const float* __restrict__ ion_tgt, const float* __restrict__ wc_tgt,
+                                                 float* __restrict__ Z, unsigned short* __restrict__ H,
+                                                 float* __restrict__ dC, double* __restrict__ loss_part, float gscale) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  FwdLds& S = *reinterpret_cast<FwdLds*>(smem);
+  const int row0 = blockIdx.x * kRows;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  for (int e = tid; e < kNWeights; e += blockDim.x) S.wt[e] = wt_g[e];
+  for (int e = tid; e < kH; e += blockDim.x) {
+    S.b[e] = params[kOffB1 + e];
+    S.b[kH + e] = params[kOffB2 + e];
+    S.b[2 * kH + e] = params[kOffB3 + e];
+  }
+  for (int e = tid; e < kOut; e += blockDim.x) S.b[3 * kH + e] = params[kOffB4 + e];
+  for (int e = tid; e < kRows * kIn / 4; e += blockDim.x) {
+    const int r = e / (kIn / 4), c4 = e % (kIn / 4);
+    uint2 v = make_uint2(0u, 0u);
+    if (row0 + r < n) v = reinterpret_cast<const uint2*>(X + (size_t)(row0 + r) * kIn)[c4];
+    reinterpret_cast<uint2*>(&S.x[r][0])[c4] = v;
+  }
+  __syncthreads();
+
+  const int wr = wave * 32;  // this wave's first row in the block
+  const unsigned short* wl[4] = {S.wt, S.wt + kIn * kH, S.wt + kIn * kH + kH * kH, S.wt + kIn * kH + 2 * kH * kH};
+  // hidden layers
+#pragma unroll
+  for (int layer = 0; layer < 3; ++layer) {
+    const int K = layer == 0 ? kIn : kH;
+    const unsigned short* A = layer == 0 ? &S.x[wr][0] : &S.h[(layer - 1) & 1][wr][0];
+    const int lda = layer == 0 ? kIn : kH;
+    unsigned short* Hout = &S.h[layer & 1][wr][0];
+#pragma unroll
+    for (int nt = 0; nt < kH / 32; ++nt) {
+      f32x16 acc;
+      zero(acc);
+      // B(k, n) = W[k][n] = Wt[n][k]
+      mfma_tile(acc, A, lda, 1, wl[layer] + nt * 32 * K, 1, K, K);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = acc_row(r), col = nt * 32 + acc_col();
+        const float z = acc[r] + S.b[layer * kH + col];
+        const float h = silu(z);
+        const unsigned short hb = f2bf(h);
+        Hout[row * kH + col] = hb;
+        if (TRAIN && row0 + wr + row < n) {
+          Z[((size_t)layer * n + row0 + wr + row) * kH + col] = z;
+          H[((size_t)layer * n + row0 + wr + row) * kH + col] = hb;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // output layer: c = h3 W4 + b4
+  {
+    f32x16 acc;
+    zero(acc);
+    mfma_tile(acc, &S.h[0][wr][0], kH, 1, wl[3], 1, kH, kH);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) S.c[wr + acc_row(r)][acc_col()] = acc[r] + S.b[3 * kH + acc_col()];
+  }
+  __syncthreads();
+
+  // head: one thread per particle (threads 0..127)
+  double lsum = 0.0;
+  if (tid < kRows && row0 + tid < n) {
+    const int slot = row0 + tid;
+    const float* Tp = Tin + (size_t)slot * 128;
+    const float q = cpos[slot].w;
+    float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+#pragma unroll 8
+    for (int k = 0; k < kOut; ++k) {
+      const float4 t = reinterpret_cast<const float4*>(Tp)[k];
+      const float cc = S.c[tid][k];
+      f0 += cc * t.y;
+      f1 += cc * t.z;
+      f2 += cc * t.w;
+    }
+    const float sq = s_out * q;
+    f0 *= sq; f1 *= sq; f2 *= sq;
+    const int src = cidx[slot];
+    float* out = (src < n_ion) ? ion_dF + 3 * (int64_t)src : wc_dF + 3 * ((int64_t)src - n_ion);
+    if (accumulate) { out[0] += f0; out[1] += f1; out[2] += f2; }
+    else { out[0] = f0; out[1] = f1; out[2] = f2; }
+    if (TRAIN) {
+      const float* tg = (src < n_ion) ? ion_tgt + 3 * (int64_t)src : wc_tgt + 3 * ((int64_t)src - n_ion);
+      const float e0 = f0 - tg[0], e1 = f1 - tg[1], e2 = f2 - tg[2];
+      lsum = (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
+      // dL/d dF = gscale * e (gscale = 2 / (3 n)); dL/dc_k = s_out q (g . T[k, 1:4])
+      const float g0 = gscale * e0 * sq, g1 = gscale * e1 * sq, g2 = gscale * e2 * sq;
+#pragma unroll 8
+      for (int k = 0; k < kOut; ++k) {
+        const float4 t = reinterpret_cast<const float4*>(Tp)[k];
+        dC[(size_t)slot * kOut + k] = g0 * t.y + g1 * t.z + g2 * t.w;
+      }
+    }
+  }
+  if (TRAIN) {
+    // deterministic block sum of the squared errors (threads 0..127 hold them)
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
+    if ((tid & 63) == 0) S.lred[wave] = lsum;
+    __syncthreads();
+    if (tid == 0) loss_part[blockIdx.x] = S.lred[0] + S.lred[1] + S.lred[2] + S.lred[3];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MLP backward for one block of 128 particles: per-block partial gradients of
+// every weight and bias, written to gpart[block][kNTrain] (summed later in a
+// fixed order).  Weights are staged in LDS in their natural [in][out] layout.
+// ---------------------------------------------------------------------------
+struct BwdLds {
+  unsigned short w[kNWeights];          // W1 [128][64], W2 [64][64], W3 [64][64], W4 [64][32]
+  unsigned short act[kRows][kIn];       // layer input (x or h), bf16
+  unsigned short dz[kRows][kH];         // gradient at the layer output (bf16)
+  unsigned short dzn[kRows][kH];        // gradient passed down (bf16)
+};
+
+__global__ void __launch_bounds__(256) k_mlp_bwd(const unsigned short* __restrict__ X, const float* __restrict__ Z,
+                                                 const unsigned short* __restrict__ H, const float* __restrict__ dC,
+                                                 int n, const unsigned short* __restrict__ w_g,
+                                                 float* __restrict__ gpart) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  BwdLds& S = *reinterpret_cast<BwdLds*>(smem);
+  const int row0 = blockIdx.x * kRows;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  float* gp = gpart + (size_t)blockIdx.x * kNTrain;
+  for (int e = tid; e < kNWeights; e += blockDim.x) S.w[e] = w_g[e];
+  // dz <- dC (bf16, zero for rows past n)
+  for (int e = tid; e < kRows * kOut; e += blockDim.x) {
+    const int r = e / kOut, k = e % kOut;
+    S.dz[r][k] = (row0 + r < n) ? f2bf(dC[(size_t)(row0 + r) * kOut + k]) : (unsigned short)0;
+  }
+  const int offW[4] = {0, kIn * kH, kIn * kH + kH * kH, kIn * kH + 2 * kH * kH};
+  const int offGW[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
+  const int offGB[4] = {kOffB1, kOffB2, kOffB3, kOffB4};
+  const int nin[4] = {kIn, kH, kH, kH};
+  const int nout[4] = {kH, kH, kH, kOut};
+  for (int layer = 3; layer >= 0; --layer) {
+    const int ni = nin[layer], no = nout[layer];
+    // layer input activation (x for layer 0, h_layer otherwise)
+    for (int e = tid; e < kRows * ni; e += blockDim.x) {
+      const int r = e / ni, k = e % ni;
+      unsigned short v = 0;
+      if (row0 + r < n) v = layer == 0 ? X[(size_t)(row0 + r) * kIn + k] : H[((size_t)(layer - 1) * n + row0 + r) * kH + k];
+      S.act[r][k] = v;
+    }
+    __syncthreads();
+    // weight gradient tiles: dW (ni x no) = act^T (ni x rows) * dz (rows x no)
+    const int tm = ni / 32, tn = no / 32;
+    for (int t = wave; t < tm * tn; t += 4) {
+      const int mi = t / tn, nj = t % tn;
+      f32x16 acc;
+      zero(acc);
+      // A(m, k) = act[k][m0 + m], B(k, n) = dz[k][n0 + n]
+      mfma_tile(acc, &S.act[0][mi * 32], 1, kIn, &S.dz[0][nj * 32], kH, 1, kRows);
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        gp[offGW[layer] + (mi * 32 + acc_row(r)) * no + nj * 32 + acc_col()] = acc[r];
+    }
+    // bias gradient: column sums of dz (fixed order)
+    for (int col = tid; col < no; col += blockDim.x) {
+      float s = 0.0f;
+      for (int r = 0; r < kRows; ++r) s += bf2f(S.dz[r][col]);
+      gp[offGB[layer] + col] = s;
+    }
+    if (layer == 0) break;
+    // gradient to the layer below: dh (rows x ni) = dz (rows x no) * W^T, then * silu'(z)
+    for (int t = wave; t < (kRows / 32) * (ni / 32); t += 4) {
+      const int ri = t / (ni / 32), mj = t % (ni / 32);
+      f32x16 acc;
+      zero(acc);
+      // A(m, k) = dz[r0 + m][k], B(k, n) = W[m0 + n][k]  (W stored [in][out])
+      mfma_tile(acc, &S.dz[ri * 32][0], kH, 1, S.w + offW[layer] + mj * 32 * no, 1, no, no);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = ri * 32 + acc_row(r), col = mj * 32 + acc_col();
+        float v = 0.0f;
+        if (row0 + row < n) v = acc[r] * dsilu(Z[((size_t)(layer - 1) * n + row0 + row) * kH + col]);
+        S.dzn[row][col] = f2bf(v);
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < kRows * kH; e += blockDim.x) (&S.dz[0][0])[e] = (&S.dzn[0][0])[e];
+    __syncthreads();
+  }
+}
+
+// Sum of the per-block gradient partials in block order (deterministic) and
+// of the loss partials; gscale_loss converts the squared-error sum to the mean.
+__global__ void k_grad_reduce(const float* __restrict__ gpart, int nblk, float* __restrict__ grad,
+                              const double* __restrict__ loss_part, double loss_scale, double* __restrict__ loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < kNTrain) {
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += gpart[(size_t)b * kNTrain + p];
+    grad[p] = s;
+  }
+  if (p == 0 && loss) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += loss_part[b];
+    *loss = s * loss_scale;
+  }
+}
+
+// Adam on the FP32 master parameters, then bf16 copies of the weights in
+// both layouts ([in][out] for backward, [out][in] for forward).
+__global__ void k_adam(float* __restrict__ params, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ grad, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kNTrain) return;
+  const float g = grad[p];
+  const float mm = b1 * m[p] + (1.0f - b1) * g;
+  const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+  m[p] = mm;
+  v[p] = vv;
+  params[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+__global__ void k_weights_to_bf16(const float* __restrict__ params, unsigned short* __restrict__ w,
+                                  unsigned short* __restrict__ wt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kNWeights) return;
+  // locate layer
+  int off = 0, pofs = 0, ni = kIn, no = kH;
+  if (e < kIn * kH) { off = 0; pofs = kOffW1; ni = kIn; no = kH; }
+  else if (e < kIn * kH + kH * kH) { off = kIn * kH; pofs = kOffW2; ni = kH; no = kH; }
+  else if (e < kIn * kH + 2 * kH * kH) { off = kIn * kH + kH * kH; pofs = kOffW3; ni = kH; no = kH; }
+  else { off = kIn * kH + 2 * kH * kH; pofs = kOffW4; ni = kH; no = kOut; }
+  const int loc = e - off;
+  const int i = loc / no, o = loc % no;
+  const unsigned short b = f2bf(params[pofs + loc]);
+  w[e] = b;                      // [in][out]
+  wt[off + o * ni + i] = b;      // [out][in]
+}
+
+}  // namespace mlp
+}  // namespace dplr

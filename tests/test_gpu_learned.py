@@ -1,0 +1,148 @@
+"""GPU learned coarse-mesh correction against its FP64 oracle: descriptor,
+BF16-MFMA forward (oracle with bf16 rounding at the kernel's rounding points),
+gradients of every parameter, the Adam update, training on residuals the
+library's own plans generate, and the guarded fallback to the fine mesh."""
+import numpy as np
+import pytest
+
+import systems
+from oracle import learned as OL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def small():
+    return systems.workload(1).system()
+
+
+def _t(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def _rounded(s):
+    return s.rounded(np.float32)
+
+
+def _oracle_TD(s):
+    return OL.descriptor(s.all_pos(), s.all_q(), s.box)
+
+
+def test_descriptor_matches_oracle(torch, small):
+    from paper_2504_15508_amd.learned import Mlp
+    s = _rounded(small)
+    m = Mlp(s.n)
+    T, order = m.descriptor(s.box, _t(torch, s.ion_pos), _t(torch, s.ion_q), _t(torch, s.wc_pos), _t(torch, s.wc_q))
+    Tg = np.zeros((s.n, 32, 4))
+    Tg[order.cpu().numpy()] = T.double().cpu().numpy()
+    T0, _ = _oracle_TD(s)
+    err = np.abs(Tg - T0).max() / np.abs(T0).max()
+    print(f"descriptor max rel err {err:.2e}")
+    assert err < 2e-5
+    assert sorted(order.cpu().numpy().tolist()) == list(range(s.n))
+
+
+def _params_for(s, seed):
+    T0, D0 = _oracle_TD(s)
+    p = OL.init_params(seed)
+    rng = np.random.default_rng(seed + 10)
+    for k in ("b1", "b2", "b3", "b4"):
+        p[k] = rng.normal(0, 0.1, p[k].shape)
+    mu, isd = D0.mean(0), 1.0 / (D0.std(0) + 1e-6 * (np.abs(D0).max() + 1))
+    return p, mu, isd, T0, D0
+
+
+def _pack(p, mu, isd):
+    from paper_2504_15508_amd import learned as L
+    return L.pack({**p, "mu": mu, "inv_sigma": isd})
+
+
+def test_forward_matches_oracle(torch, small):
+    from paper_2504_15508_amd.learned import Mlp
+    s = _rounded(small)
+    p, mu, isd, T0, D0 = _params_for(s, 3)
+    m = Mlp(s.n, out_scale=0.01)
+    m.set_params(_pack(p, mu, isd))
+    di, dw = m.forward(s.box, _t(torch, s.ion_pos), _t(torch, s.ion_q), _t(torch, s.wc_pos), _t(torch, s.wc_q))
+    dF = np.concatenate([di.double().cpu().numpy(), dw.double().cpu().numpy()])
+    ref, _ = OL.forward(p, T0, D0, s.all_q(), mu, isd, 0.01, emulate_bf16=True)
+    ref64, _ = OL.forward(p, T0, D0, s.all_q(), mu, isd, 0.01, emulate_bf16=False)
+    e = np.linalg.norm(dF - ref) / np.linalg.norm(ref)
+    e64 = np.linalg.norm(dF - ref64) / np.linalg.norm(ref64)
+    print(f"forward rel err vs bf16-emulating oracle {e:.2e}, vs FP64 oracle {e64:.2e}")
+    assert e < 5e-3
+    assert e64 < 5e-2
+
+
+def test_gradients_and_adam_match_oracle(torch, small):
+    from paper_2504_15508_amd import learned as L
+    s = _rounded(small)
+    p, mu, isd, T0, D0 = _params_for(s, 5)
+    target = np.random.default_rng(9).normal(0, 0.05, (s.n, 3))
+    m = L.Mlp(s.n, out_scale=0.01)
+    m.set_params(_pack(p, mu, isd))
+    args = [_t(torch, s.ion_pos), _t(torch, s.ion_q), _t(torch, s.wc_pos), _t(torch, s.wc_q),
+            _t(torch, target[: s.n_ion]), _t(torch, target[s.n_ion:])]
+    loss, g = m.train_step(s.box, *args, lr=0.0, want_grad=True)
+    dF, cache = OL.forward(p, T0, D0, s.all_q(), mu, isd, 0.01, emulate_bf16=True)
+    loss0, g0 = OL.loss_and_grad(p, cache, dF, target)
+    assert abs(float(loss) - loss0) <= 1e-3 * loss0
+    gd = L.unpack(np.concatenate([g.cpu().numpy(), np.zeros(256, np.float32)]))
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"):
+        e = np.linalg.norm(gd[k] - g0[k]) / np.linalg.norm(g0[k])
+        print(f"grad {k}: rel err {e:.2e}")
+        assert e < 3e-2, k
+    # one Adam step with the GPU's own gradient reproduces the oracle update
+    before = m.get_params()
+    loss, g = m.train_step(s.box, *args, lr=1e-3, want_grad=True)
+    after = m.get_params()
+    grads = L.unpack(np.concatenate([g.cpu().numpy(), np.zeros(256, np.float32)]))
+    ref = {k: before[k].astype(np.float64) for k in ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")}
+    OL.adam_step(ref, {k: grads[k].astype(np.float64) for k in ref}, {}, lr=1e-3)
+    for k in ref:
+        assert np.allclose(after[k], ref[k], atol=2e-6, rtol=1e-5), k
+
+
+def test_training_beats_coarse_mesh_on_heldout(torch):
+    from paper_2504_15508_amd import learned as L
+    boxes = [systems.training_box(i) for i in range(24)]
+    held = [systems.training_box(i, heldout=True) for i in range(3)]
+    mlp, rep = L.train(boxes, held, coarse_mesh=16, fine_mesh=32, epochs=6, lr=3e-3, log=print)
+    print(f"held-out rel force error vs fine mesh: learned {rep.heldout_rel_rmse_learned:.4e}, "
+          f"coarse {rep.heldout_rel_rmse_coarse:.4e}; loss {rep.losses[0]:.3e} -> {rep.losses[-1]:.3e}")
+    assert rep.losses[-1] < rep.losses[0]
+    assert rep.heldout_rel_rmse_learned < rep.heldout_rel_rmse_coarse
+
+
+def test_guard_audits_then_falls_back(torch):
+    from paper_2504_15508_amd import learned as L
+    from paper_2504_15508_amd.plan import Plan
+    s = systems.training_box(0)
+    coarse = Plan(16, order=5, precision="fp32", capacity=s.n)
+    fine = Plan(32, order=8, precision="fp32", capacity=s.n)
+    coarse.set_box(s.box)
+    fine.set_box(s.box)
+    m = L.Mlp(s.n)
+    m.set_params(L.init_params(0))
+    lc = L.LearnedCoarse(s.box, coarse, fine, m, guard_cfg=dict(max_audit_rel_rmse=1e-3, audit_interval=5))
+    args = [_t(torch, s.ion_pos), _t(torch, s.ion_q), _t(torch, s.wc_pos), _t(torch, s.wc_q)]
+    modes = [lc.compute(*args)[4] for _ in range(3)]
+    # first call audits; an untrained correction misses 1e-3, so the guard falls back
+    assert modes[0] == "audit" and modes[1:] == ["fine", "fine"]
+    assert lc.stats["audit_rel_rmse"] > 1e-3
+    # with a loose tolerance the learned form runs until the next audit is due
+    lc2 = L.LearnedCoarse(s.box, coarse, fine, m, guard_cfg=dict(max_audit_rel_rmse=1.0, audit_interval=3))
+    modes2 = [lc2.compute(*args)[4] for _ in range(5)]
+    assert modes2 == ["audit", "learned", "learned", "learned", "audit"]
+    # unseen charges (Na+ / Cl- are absent from the water training set) force the fine mesh
+    q = args[1].clone()
+    q[0] = 1.5
+    assert lc2.compute(args[0], q, args[2], args[3])[4] == "fine"
