@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the order-8 and accuracy legs")
     ap.add_argument("--eager-only", action="store_true", help="no graph capture (profiling runs)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned coarse-mesh leg")
+    ap.add_argument("--learned-boxes", type=int, default=2000, help="training boxes for the learned leg")
+    ap.add_argument("--learned-epochs", type=int, default=3)
     return ap.parse_args()
 
 
@@ -121,12 +124,87 @@ def cpu_baseline():
                       "costs O(N^2) at fixed density, so the full 288,768-charge system runs ~8x slower per charge"}
 
 
+def learned_leg(args, w, s0, ion_d, wc_d, qi, qw, dev, timed_graph_fn, plain_ms, gold):
+    """Learned coarse form: train the correction on spacing-matched boxes
+    (1,128 waters in 32.325 A, meshes 16^3 / 32^3 = the spacings of 64^3 /
+    128^3 here), then evaluate 64^3 + correction on frame 0 against the stored
+    Ewald forces and time it as the plain step is timed."""
+    import numpy as np
+    import torch
+    import systems
+    import paper_2504_15508_amd as dl
+    from paper_2504_15508_amd import learned as L
+
+    t0 = time.perf_counter()
+    boxes = [systems.training_box(i) for i in range(args.learned_boxes)]
+    held = [systems.training_box(i, heldout=True) for i in range(max(1, args.learned_boxes // 10))]
+    log(f"learned leg: training on {len(boxes)} boxes x {args.learned_epochs} epochs")
+    mlp = L.Mlp(s0.n, device=dev)
+    mlp, rep = L.train(boxes, held, coarse_mesh=16, fine_mesh=32, epochs=args.learned_epochs, lr=2e-3, mlp=mlp,
+                       device=dev, log=lambda m: log("  " + m))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del boxes, held
+
+    coarse = dl.Plan(w.coarse_mesh, order=w.order, beta=w.beta, coulomb_k=w.coulomb_k, precision="fp32",
+                     capacity=s0.n, device=dev)
+    coarse.set_box(s0.box)
+    fine = dl.Plan(w.mesh, order=w.order, beta=w.beta, coulomb_k=w.coulomb_k, precision="fp32",
+                   capacity=s0.n, device=dev)
+    fine.set_box(s0.box)
+    r0 = torch.tensor(s0.ion_pos, dtype=torch.float32, device=dev)
+    w0 = torch.tensor(s0.wc_pos, dtype=torch.float32, device=dev)
+    out = {"learned_train_boxes": args.learned_boxes, "learned_train_epochs": args.learned_epochs,
+           "learned_train_seconds": train_s,
+           "learned_heldout_rel_rmse_vs_fine": rep.heldout_rel_rmse_learned,
+           "coarse_heldout_rel_rmse_vs_fine": rep.heldout_rel_rmse_coarse}
+    idx = np.array(gold["sample_index"]) if gold else None
+    fref = np.array(gold["sample_force"]) if gold else None
+
+    def rmse(a, b):
+        F = torch.cat([a, b]).double().cpu().numpy()[idx]
+        return float(np.linalg.norm(F - fref) / np.linalg.norm(fref))
+
+    _, ci, cw, _ = coarse.compute(r0, qi, w0, qw)
+    ci, cw = ci.clone(), cw.clone()
+    di, dw = mlp.forward(s0.box, r0, qi, w0, qw)
+    if gold:
+        out["coarse64_force_rmse_vs_ewald"] = rmse(ci, cw)
+        out["learned64_force_rmse_vs_ewald"] = rmse(ci + di, cw + dw)
+    # guarded driver: first call audits against the 128^3 plan
+    lc = L.LearnedCoarse(s0.box, coarse, fine, mlp, guard_cfg=dict(max_audit_rel_rmse=1e-3))
+    modes = [lc.compute(r0, qi, w0, qw)[4] for _ in range(2)]
+    out["learned_audit_rel_rmse_vs_128"] = lc.stats["audit_rel_rmse"]
+    out["learned_guard_modes"] = modes
+
+    # timing: coarse plan + descriptor + network, one captured graph per K steps
+    fi = torch.empty((s0.n_ion, 3), dtype=torch.float32, device=dev)
+    fw = torch.empty((s0.n_wc, 3), dtype=torch.float32, device=dev)
+    e = torch.empty((), dtype=torch.float64, device=dev)
+    v = torch.empty(6, dtype=torch.float64, device=dev)
+
+    def lstep(t):
+        coarse.compute(ion_d[t], qi, wc_d[t], qw, ion_force=fi, wc_force=fw, energy=e, virial=v)
+        mlp.forward(s0.box, ion_d[t], qi, wc_d[t], qw, fi, fw, accumulate=True)
+
+    def cstep(t):
+        coarse.compute(ion_d[t], qi, wc_d[t], qw, ion_force=fi, wc_force=fw, energy=e, virial=v)
+
+    out["learned64_ms_per_step"] = 1e3 * timed_graph_fn(lstep)
+    out["coarse64_ms_per_step"] = 1e3 * timed_graph_fn(cstep)
+    out["plain128_ms_per_step"] = plain_ms
+    coarse.close()
+    fine.close()
+    mlp.close()
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, "
-              "'How the path would shard'); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1.",
+              file=sys.stderr)
         return 2
 
     import numpy as np
@@ -171,19 +249,20 @@ def main():
     def step(p, t):
         p.compute(ion_d[t], qi, wc_d[t], qw, ion_force=f_ion, wc_force=f_wc, energy=energy[t], virial=virial[t])
 
-    def timed_graph(p):
+    def timed_graph(fn):
+        """K steps fn(W), ..., fn(W + K - 1) replayed from one captured graph."""
         stream = torch.cuda.Stream(device=dev)
         torch.cuda.synchronize()
         gw, gt = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
         with torch.cuda.stream(stream):
-            step(p, 0)               # binds the plan to the capture stream outside capture
+            fn(0)                    # binds the plans to the capture stream outside capture
         torch.cuda.synchronize()
         with torch.cuda.graph(gw, stream=stream):
             for t in range(W):
-                step(p, t)
+                fn(t)
         with torch.cuda.graph(gt, stream=stream):
             for t in range(W, W + K):
-                step(p, t)
+                fn(t)
         gw.replay()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -213,7 +292,7 @@ def main():
         sec = None
     else:
         log("timed region: graph replay")
-        sec = timed_graph(plan)
+        sec = timed_graph(lambda t: step(plan, t))
     log("eager pass with per-kernel HIP events")
     eager_sec, prof = timed_eager(plan, True)
     if sec is None:
@@ -245,10 +324,18 @@ def main():
                     extras[f"order{order}_force_rmse_vs_ewald"] = float(np.linalg.norm(F - fref) / np.linalg.norm(fref))
                     extras[f"order{order}_energy_relerr_vs_ewald"] = abs(float(E) - gold["energy"]) / abs(gold["energy"])
                     if order != args.order:
-                        extras[f"order{order}_ms_per_step"] = 1e3 * (timed_graph(p) if not args.eager_only
+                        extras[f"order{order}_ms_per_step"] = 1e3 * (timed_graph(lambda t: step(p, t)) if not args.eager_only
                                                                      else timed_eager(p, False)[0])
         except Exception as e:  # extras never hide the headline measurement
             extras["extras_error"] = repr(e)
+    if not args.no_learned and not args.eager_only:
+        try:
+            gpath = os.path.join(ROOT, "tests", "golden", f"ewald_{w.name}.json")
+            gold = json.load(open(gpath)) if os.path.exists(gpath) else None
+            extras.update(learned_leg(args, systems.workload(4), s0, ion_d, wc_d, qi, qw, dev, timed_graph, ms,
+                                      gold))
+        except Exception as e:
+            extras["learned_error"] = repr(e)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -97,25 +97,40 @@ __device__ __forceinline__ void dft_small(cpx<T>* v) {
 __device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
 __host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4); }
 
+// 24-bit integer products (full rate on CDNA; 32-bit products issue at a
+// quarter of the rate).  Every LDS index and mesh index fits.
+__device__ __forceinline__ int imul(int a, int b) { return (int)__umul24((unsigned)a, (unsigned)b); }
+
 template <typename T, int R, bool INV, int EPT, bool PAD>
-__device__ __forceinline__ void fft_stage(cpx<T>* buf, int nrows, int N, int rstride, int estride,
+__device__ __forceinline__ void fft_stage(cpx<T>* buf, int nrows, float inv_nrows, int N, int rstride, int estride,
                                           bool rows_fast, int Ns, const cpx<T>* tw, int twN) {
   constexpr int BPT = (EPT + R - 1) / R;
   const int nb = N / R;
   const int lnb = 31 - __clz(nb);  // nb is a power of two
-  const int total = nrows * nb;
+  const int total = imul(nrows, nb);
+  // (butterfly b) -> (row, j); with rows fastest, j = floor(b / nrows) is formed
+  // as (b + 1/2) / nrows in FP32, exact for b < 2^20
+  auto split = [&](int b, int& row, int& j) {
+    if (rows_fast) {
+      j = (int)(((float)b + 0.5f) * inv_nrows);
+      row = b - imul(j, nrows);
+    } else {
+      j = b & (nb - 1);
+      row = b >> lnb;
+    }
+  };
   cpx<T> v[BPT][R];
 #pragma unroll
   for (int c = 0; c < BPT; ++c) {
     const int b = threadIdx.x + c * blockDim.x;
     if (b < total) {
       int row, j;
-      if (rows_fast) { j = b / nrows; row = b - j * nrows; } else { j = b & (nb - 1); row = b >> lnb; }
-      const cpx<T>* base = buf + row * rstride;
+      split(b, row, j);
+      const cpx<T>* base = buf + imul(row, rstride);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int e = j + r * nb;
-        v[c][r] = base[PAD ? lds_pad(e) : e * estride];
+        v[c][r] = base[PAD ? lds_pad(e) : imul(e, estride)];
       }
     }
   }
@@ -126,23 +141,24 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int nrows, int N, int rst
     const int b = threadIdx.x + c * blockDim.x;
     if (b < total) {
       int row, j;
-      if (rows_fast) { j = b / nrows; row = b - j * nrows; } else { j = b & (nb - 1); row = b >> lnb; }
+      split(b, row, j);
       const int k = j & (Ns - 1);
       if (Ns > 1) {
+        const int kt = imul(k, twstep);
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cpx<T> w = tw[r * k * twstep];
+          cpx<T> w = tw[r * kt];
           if (INV) w.y = -w.y;
           v[c][r] = cmul(v[c][r], w);
         }
       }
       dft_small<T, R, INV>(v[c]);
-      cpx<T>* base = buf + row * rstride;
+      cpx<T>* base = buf + imul(row, rstride);
       const int o = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int e = o + r * Ns;
-        base[PAD ? lds_pad(e) : e * estride] = v[c][r];
+        base[PAD ? lds_pad(e) : imul(e, estride)] = v[c][r];
       }
     }
   }
@@ -152,17 +168,18 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int nrows, int N, int rst
 // Full transform: radix-8 stages while that leaves a length of 4 or more
 // (or exactly 1), radix-4 for the rest.  N is a power of two >= 4.
 template <typename T, bool INV, int EPT, bool PAD = false>
-__device__ void fft_rows(cpx<T>* buf, int nrows, int N, int rstride, int estride, bool rows_fast,
-                         const cpx<T>* tw, int twN) {
+__device__ __forceinline__ void fft_rows(cpx<T>* buf, int nrows, int N, int rstride, int estride, bool rows_fast,
+                                         const cpx<T>* tw, int twN) {
+  const float inv_nrows = 1.0f / (float)nrows;
   int lg = 31 - __clz(N);
   int Ns = 1;
   while (lg > 0) {
     if (lg >= 3 && lg - 3 != 1) {
-      fft_stage<T, 8, INV, EPT, PAD>(buf, nrows, N, rstride, estride, rows_fast, Ns, tw, twN);
+      fft_stage<T, 8, INV, EPT, PAD>(buf, nrows, inv_nrows, N, rstride, estride, rows_fast, Ns, tw, twN);
       Ns *= 8;
       lg -= 3;
     } else {
-      fft_stage<T, 4, INV, EPT, PAD>(buf, nrows, N, rstride, estride, rows_fast, Ns, tw, twN);
+      fft_stage<T, 4, INV, EPT, PAD>(buf, nrows, inv_nrows, N, rstride, estride, rows_fast, Ns, tw, twN);
       Ns *= 4;
       lg -= 2;
     }

@@ -25,6 +25,13 @@ thread_local std::string g_global_error;
 #ifndef DPLR_GATHER_MIN_THREADS
 #define DPLR_GATHER_MIN_THREADS 256
 #endif
+// spread blocks the x splits aim for (two per compute unit on a 256-CU part)
+#ifndef DPLR_SPREAD_TARGET_BLOCKS
+#define DPLR_SPREAD_TARGET_BLOCKS 512
+#endif
+#ifndef DPLR_SPREAD_MAX_SPLIT
+#define DPLR_SPREAD_MAX_SPLIT 8
+#endif
 
 constexpr int kMinMesh = 16;
 constexpr int kMaxMesh = 512;
@@ -76,12 +83,14 @@ struct dplr_lr_plan_s {
   bool has_box = false;
   size_t lds_budget = 65536;
   size_t lds_spread = 0, lds_ffty = 0, lds_z = 0, lds_ifftx = 0;
+  bool plane = false;         // whole z planes fit in LDS: spread + x and y transforms in one kernel
   int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_ifftx = 256;
   // device workspace
   int* bin_count = nullptr;
   int* bin_start = nullptr;
   int* bin_cursor = nullptr;
   int* bin_hist = nullptr;    // [max chunks][nbins]
+  unsigned* qmax = nullptr;   // max |q| bits: per sort chunk, or one word (global-atomic sort)
   bool block_hist = false;    // bins fit in LDS: sort without global atomics
   int max_chunks = 256;
   void* sorted = nullptr;
@@ -108,8 +117,8 @@ struct dplr_lr_plan_s {
 namespace {
 
 const char* const kStageNames[] = {"bin_count", "bin_scan", "bin_scatter", "spread_fftx", "ffty_fwd",
-                                   "fftz_poisson", "ffty_inv_reduce", "ifftx", "gather"};
-constexpr int kNumStages = 9;
+                                   "fftz_poisson", "ffty_inv_reduce", "ifftx", "gather", "spread_xy"};
+constexpr int kNumStages = 10;
 
 hipEvent_t prof_event(dplr_lr_plan p) {
   if (!p->prof_pool.empty()) {
@@ -163,32 +172,73 @@ bool choose_geometry(dplr_lr_plan p) {
   const size_t ts = p->tsize, cs = 2 * ts;
   g.K[0] = Kx; g.K[1] = Ky; g.K[2] = Kz;
   g.Kh = Kx / 2 + 1;
-  g.NQ = Ky / 4;
-  g.nbins = Kz * g.NQ;
+  g.qshift = 2;
+  g.NQ = Ky >> g.qshift;
   g.twN = std::max(Kx, std::max(Ky, Kz));
   const size_t twb = g.twN * cs;
   const size_t budget = p->lds_budget - 1024;  // static LDS (ranges, reductions)
 
-  const int cand[][2] = {{16, 4}, {8, 4}, {16, 2}, {8, 2}, {4, 4}, {4, 2}, {8, 1}, {4, 1}};
-  g.scy = 0;
+  // plane spread: one z plane of 64-bit accumulators (rows of Kx + p - 1),
+  // reused for the x- and y-transform tiles, 1024 threads holding at most 16
+  // values each
+  {
+    const size_t b_acc = (size_t)Ky * (Kx + P - 1) * sizeof(long long);
+    const size_t b_tx = (size_t)(Ky / 2) * (padded_len(Kx) + 1) * cs;
+    const size_t b_ty = (size_t)g.Kh * (padded_len(Ky) + 1) * cs;
+    const size_t b = std::max(b_acc, std::max(b_tx, b_ty)) + twb;
+    p->plane = b <= budget && (long)Kx * Ky <= 16L * 1024 && (long)g.Kh * Ky <= 16L * 1024;
+    if (p->plane) {
+      p->lds_spread = b;
+      p->thr_spread = 1024;
+      const int per_cu = std::max<int>(1, (int)(p->lds_budget / (b + 1024)));
+      const int target = std::min(1024, 256 * per_cu);
+      g.nsplit = 1;
+      while (Kz * g.nsplit < target && g.nsplit < DPLR_SPREAD_MAX_SPLIT && Kx / (2 * g.nsplit) >= 4) g.nsplit *= 2;
+      g.xs = Kx / g.nsplit;
+      // a plane visits all row groups of its planes: coarse groups keep the
+      // sort small while consecutive particles stay close in y
+      g.qshift = std::min(4, 31 - __builtin_clz((unsigned)Ky));
+      g.NQ = Ky >> g.qshift;
+      g.nbins = g.nsplit * Kz * g.NQ;
+      g.scy = Ky; g.scz = 1; g.spy = 1; g.spz = Kz;
+    }
+  }
+  // spread pencils: two blocks of at most 512 threads per compute unit, so a
+  // block gets half of the LDS; the largest cross-section that fits wins
+  // (fewest particles visited twice)
+  const size_t sbudget = std::min(budget, p->lds_budget / 2 - 1024);
+  const int cand[][2] = {{16, 8}, {16, 4}, {8, 4}, {16, 2}, {8, 2}, {4, 4}, {4, 2}, {8, 1}, {4, 1}};
+  if (!p->plane) g.scy = 0;
   for (auto& c : cand) {
+    if (p->plane) break;
     const int cy = c[0], cz = c[1];
     if (cy > Ky || cz > Kz || (cy * cz) % 2) continue;
-    // 64-bit fixed-point accumulators, converted in place to padded complex pairs
-    const size_t accb = (size_t)cy * cz * Kx * sizeof(long long);
+    // 64-bit fixed-point accumulators (rows of Kx + p - 1), converted in
+    // place to padded complex pairs
+    const size_t accb = (size_t)cy * cz * (Kx + P - 1) * sizeof(long long);
     const size_t cpxb = (size_t)(cy * cz / 2) * (padded_len(Kx) + 1) * cs;
     const size_t b = std::max(accb, cpxb) + twb;
     const long long elems = (long long)cy * cz * Kx;
-    if (b <= budget && elems <= 16LL * 1024) {
+    if (b <= sbudget && elems <= 16LL * 512) {
       g.scy = cy; g.scz = cz; p->lds_spread = b;
       break;
     }
   }
-  if (!g.scy) return false;
-  g.spy = Ky / g.scy; g.spz = Kz / g.scz;
-  // the in-place fixed-point conversion holds at most 16 values per thread
-  p->thr_spread = std::max(DPLR_SPREAD_MIN_THREADS, round_threads((long)g.scy * g.scz / 2 * Kx));
-  while ((long)p->thr_spread * 16 < (long)g.scy * g.scz * Kx && p->thr_spread < 1024) p->thr_spread += 64;
+  if (!p->plane) {
+    if (!g.scy) return false;
+    g.spy = Ky / g.scy; g.spz = Kz / g.scz;
+    // the in-place fixed-point conversion holds at most 16 values per thread
+    p->thr_spread = std::max(DPLR_SPREAD_MIN_THREADS, round_threads((long)g.scy * g.scz / 2 * Kx));
+    while ((long)p->thr_spread * 16 < (long)g.scy * g.scz * Kx && p->thr_spread < 512) p->thr_spread += 64;
+    if ((long)p->thr_spread * 16 < (long)g.scy * g.scz * Kx || p->thr_spread > 512) return false;
+    // x splits: more blocks when the pencils alone do not fill the device
+    g.nsplit = 1;
+    while (g.spy * g.spz * g.nsplit < DPLR_SPREAD_TARGET_BLOCKS && g.nsplit < DPLR_SPREAD_MAX_SPLIT &&
+           Kx / (2 * g.nsplit) >= 8)
+      g.nsplit *= 2;
+    g.xs = Kx / g.nsplit;
+    g.nbins = g.nsplit * Kz * g.NQ;
+  }
 
   // inverse x pass: xyb rows of y of the three fields per block
   g.xyb = std::min(16, Ky);
@@ -250,6 +300,7 @@ void set_lds_attrs(dplr_lr_plan p) {
 #define DPLR_ATTR(PP)                                                        \
   case PP:                                                                   \
     attr((const void*)k_spread_fftx<T, PP>, p->lds_spread);                  \
+    attr((const void*)k_spread_xy<T, PP>, p->lds_spread);                    \
     break;
     DPLR_ATTR(2) DPLR_ATTR(3) DPLR_ATTR(4) DPLR_ATTR(5) DPLR_ATTR(6) DPLR_ATTR(7) DPLR_ATTR(8)
 #undef DPLR_ATTR
@@ -281,9 +332,11 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
   T4<T>* sorted = reinterpret_cast<T4<T>*>(p->sorted);
   cpx<T>* spec = reinterpret_cast<cpx<T>*>(p->spec);
   cpx<T>* fspec = reinterpret_cast<cpx<T>*>(p->fspec);
+  const size_t nspec = (size_t)g.Kh * g.K[1] * g.K[2];
   const T* ip = (const T*)ion_pos;
   const T* wp = (const T*)wc_pos;
 
+  int nqpart = 1;  // charge-maximum words the spread reads
   if (p->block_hist) {
     // chunk size: multiple of 1024, at most max_chunks chunks
     int64_t chunk = std::max<int64_t>(1024, ((n + p->max_chunks - 1) / p->max_chunks + 1023) / 1024 * 1024);
@@ -308,8 +361,9 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
       ProfScope ps(p, 2);
       hipLaunchKernelGGL((k_bin_place<T, P>), dim3(nblk), dim3(1024), lds, s, ip, wp, (const T*)ion_q,
                          (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], p->bin_hist, p->bin_start, sorted, p->sidx,
-                         p->perm, (int)chunk, g);
+                         p->perm, p->qmax, (int)chunk, g);
     }
+    nqpart = n > 0 ? nblk : 0;
   } else {
     if (n > 0) {
       const int nb = (int)((n + 255) / 256);
@@ -320,39 +374,45 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
     {
       ProfScope ps(p, 1);
       hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, p->bin_count, p->bin_start, p->bin_cursor,
-                         g.nbins);
+                         g.nbins, p->qmax);
     }
     if (n > 0) {
       const int nb = (int)((n + 255) / 256);
       ProfScope ps(p, 2);
       hipLaunchKernelGGL((k_bin_scatter<T, P>), dim3(nb), dim3(256), 0, s, ip, wp, (const T*)ion_q, (const T*)wc_q,
-                         n_ion, n, ih[0], ih[1], ih[2], p->bin_cursor, sorted, p->sidx, p->perm, g);
+                         n_ion, n, ih[0], ih[1], ih[2], p->bin_cursor, sorted, p->sidx, p->perm, p->qmax, g);
     }
   }
-  {
-    ProfScope ps(p, 3);
-    hipLaunchKernelGGL((k_spread_fftx<T, P>), dim3(g.spy * g.spz), dim3(p->thr_spread), p->lds_spread, s, sorted,
-                       p->sidx, p->bin_start, spec, tw, g);
-  }
-  {
-    ProfScope ps(p, 4);
-    hipLaunchKernelGGL((k_ffty<T, false>), dim3(g.Kh * (g.K[2] / g.zb)), dim3(p->thr_ffty), p->lds_ffty, s, spec, tw, g,
-                       (const double*)nullptr, 0.0, (double*)nullptr, (double*)nullptr);
+  if (p->plane) {
+    ProfScope ps(p, 9);
+    hipLaunchKernelGGL((k_spread_xy<T, P>), dim3(g.K[2] * g.nsplit), dim3(p->thr_spread), p->lds_spread, s, sorted,
+                       p->sidx, p->bin_start, (const unsigned*)p->qmax, nqpart, spec, nspec, tw, g);
+  } else {
+    {
+      ProfScope ps(p, 3);
+      hipLaunchKernelGGL((k_spread_fftx<T, P>), dim3(g.spy * g.spz * g.nsplit), dim3(p->thr_spread), p->lds_spread,
+                         s, sorted, p->sidx, p->bin_start, (const unsigned*)p->qmax, nqpart, spec, nspec, tw, g);
+    }
+    {
+      ProfScope ps(p, 4);
+      hipLaunchKernelGGL((k_ffty<T, false>), dim3(g.Kh * (g.K[2] / g.zb)), dim3(p->thr_ffty), p->lds_ffty, s, spec, tw,
+                         g, g.nsplit, nspec, (const double*)nullptr, 0.0, (double*)nullptr, (double*)nullptr);
+    }
   }
   PoissonConsts pc;
   for (int a = 0; a < 3; ++a) pc.two_pi_over_L[a] = 2.0 * M_PI / p->box[a];
   pc.inv_4beta2 = 1.0 / (4.0 * p->cfg.beta * p->cfg.beta);
   {
     ProfScope ps(p, 5);
-    hipLaunchKernelGGL((k_fftz_poisson<T>), dim3(g.nzblk), dim3(p->thr_z), p->lds_z, s, spec, fspec, p->G,
-                       p->partials, tw, g, pc);
+    hipLaunchKernelGGL((k_fftz_poisson<T>), dim3(g.nzblk), dim3(p->thr_z), p->lds_z, s, spec,
+                       p->plane ? g.nsplit : 1, nspec, fspec, p->G, p->partials, tw, g, pc);
   }
   const double V = p->box[0] * p->box[1] * p->box[2];
   const bool want_virial = !(p->cfg.flags & DPLR_LR_NO_VIRIAL) && virial;
   {
     ProfScope ps(p, 6);
     hipLaunchKernelGGL((k_ffty<T, true>), dim3(3 * g.Kh * (g.K[2] / g.zb)), dim3(p->thr_ffty), p->lds_ffty, s,
-                       fspec, tw, g, (const double*)p->partials, p->cfg.coulomb_k / (2.0 * V), energy,
+                       fspec, tw, g, 1, (size_t)0, (const double*)p->partials, p->cfg.coulomb_k / (2.0 * V), energy,
                        want_virial ? virial : (double*)nullptr);
   }
   if (n > 0) {
@@ -465,7 +525,8 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
   DPLR_ALLOC(p->sorted, 4 * ts * cap, "sorted");
   DPLR_ALLOC(p->perm, sizeof(int) * cap, "perm");
   DPLR_ALLOC(p->sidx, sizeof(int) * cap, "stencil starts");
-  DPLR_ALLOC(p->spec, cs * nspec, "spectrum");
+  DPLR_ALLOC(p->spec, cs * nspec * g.nsplit, "spectrum (one partial per x split)");
+  DPLR_ALLOC(p->qmax, sizeof(unsigned) * (size_t)std::max(p->max_chunks, 1), "charge maxima");
   DPLR_ALLOC(p->fspec, 3 * cs * nspec, "field spectra");
   DPLR_ALLOC(p->field, 3 * ts * (size_t)g.K[0] * g.K[1] * g.K[2], "fields");
   DPLR_ALLOC(p->G, sizeof(double) * ng, "influence");
@@ -629,6 +690,24 @@ dplr_lr_status dplr_lr_debug_copy(dplr_lr_plan p, int32_t which, void* dst, int6
   if (size < 0) return fail(p, DPLR_LR_E_INVALID, "unknown buffer");
   if (!dst || bytes < 0 || bytes > size) return fail(p, DPLR_LR_E_INVALID, "bad destination or size");
   const void* src = which == DPLR_LR_BUF_SPECTRUM ? p->spec : which == DPLR_LR_BUF_INFLUENCE ? (const void*)p->G : p->fspec;
+  if (which == DPLR_LR_BUF_SPECTRUM && p->plane && p->geo.nsplit > 1) {
+    // the plane spread leaves one partial spectrum per x split: report their sum
+    const size_t cs = 2 * p->tsize;
+    if ((size_t)bytes % cs) return fail(p, DPLR_LR_E_INVALID, "size must be a whole number of complex values");
+    const size_t n = (size_t)bytes / cs, nspec = (size_t)size / cs;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (n > 0) {
+      if (p->fp64)
+        hipLaunchKernelGGL(k_sum_partials<double>, dim3(nb), dim3(256), 0, p->stream, (cpx<double>*)dst,
+                           (const cpx<double>*)p->spec, p->geo.nsplit, nspec, n);
+      else
+        hipLaunchKernelGGL(k_sum_partials<float>, dim3(nb), dim3(256), 0, p->stream, (cpx<float>*)dst,
+                           (const cpx<float>*)p->spec, p->geo.nsplit, nspec, n);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(p, e, "debug copy");
+    return DPLR_LR_OK;
+  }
   hipError_t e = hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, p->stream);
   if (e != hipSuccess) return hip_fail(p, e, "debug copy");
   return DPLR_LR_OK;

@@ -4,9 +4,12 @@
 //   sorted   [n] T4 (d_x, d_y, d_z, q): fractional B-spline offsets and charge,
 //            ordered by bin; sidx [n] int: stencil starts s_x | s_y<<10 | s_z<<20;
 //            perm [n] int: original index (ions 0..n_ion-1, then WCs).
-//   bins     one per (stencil-start plane s_z, stencil-start row quad s_y/4);
+//   bins     one per (x split s_x / xs, stencil-start plane s_z, stencil-start
+//            row group s_y >> qshift), in that order of significance;
 //            bin_start [nbins+1].
-//   spec     half spectrum [Kx/2+1][Kz][Ky] complex (y fastest).
+//   spec     half spectrum [Kx/2+1][Kz][Ky] complex (y fastest); the spread
+//            writes one such partial spectrum per x split, the forward y pass
+//            sums them in split order into the first.
 //   fspec    three field spectra [3][Kx/2+1][Kz][Ky] complex.
 //   G        FP64 influence table [Kx/2+1][Ky/2+1][Kz/2+1] (G is even in
 //            every wave-vector component).
@@ -25,8 +28,11 @@ struct alignas(4 * sizeof(T)) T4 {
 struct Geo {
   int K[3];      // Kx, Ky, Kz
   int Kh;        // Kx/2 + 1
-  int NQ;        // Ky / 4
-  int nbins;     // Kz * NQ
+  int qshift;    // rows per bin group = 2^qshift (4 for pencil tiles, 16 for planes)
+  int NQ;        // Ky >> qshift
+  int nsplit;    // x splits of the spread (particles binned by s_x / xs)
+  int xs;        // Kx / nsplit
+  int nbins;     // nsplit * Kz * NQ
   int scy, scz;  // spread pencil cross-section (y, z); the pencil spans all x
   int spy, spz;  // spread pencil counts
   int zb;        // rows per block of the y-transform pass
@@ -98,7 +104,19 @@ __device__ __forceinline__ void particle_bin(const T* __restrict__ ion_pos, cons
     s[a] = sa;
   }
   spack = s[0] | (s[1] << 10) | (s[2] << 20);
-  bin = s[2] * g.NQ + (s[1] >> 2);
+  bin = ((s[0] / g.xs) * g.K[2] + s[2]) * g.NQ + (s[1] >> g.qshift);
+}
+
+// |q| as an unsigned integer whose order is that of the float (non-negative
+// floats compare as their bit patterns); the wave maximum is formed with
+// shuffles so that one lane per wave touches memory.
+template <typename T>
+__device__ __forceinline__ unsigned abs_q_bits(T q) {
+  return __float_as_uint(fabsf((float)q));
+}
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, off, 64));
+  return v;
 }
 
 template <typename T, int P>
@@ -117,7 +135,9 @@ __global__ void __launch_bounds__(256) k_bin_count(const T* __restrict__ ion_pos
 // Exclusive scan of the bin counts (one block); also clears the counts for
 // the next call and seeds the scatter cursors.
 __global__ void __launch_bounds__(1024) k_bin_scan(int* __restrict__ count, int* __restrict__ start,
-                                                   int* __restrict__ cursor, int nbins) {
+                                                   int* __restrict__ cursor, int nbins,
+                                                   unsigned* __restrict__ qmax_bits = nullptr) {
+  if (qmax_bits && threadIdx.x == 0) *qmax_bits = 0u;
   __shared__ int part[1024];
   const int t = threadIdx.x, nt = blockDim.x;
   const int chunk = (nbins + nt - 1) / nt;
@@ -149,18 +169,24 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const T* __restrict__ ion_p
                                                      const T* __restrict__ ion_q, const T* __restrict__ wc_q,
                                                      int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
                                                      int* __restrict__ cursor, T4<T>* __restrict__ sorted,
-                                                     int* __restrict__ sidx, int* __restrict__ perm, Geo g) {
+                                                     int* __restrict__ sidx, int* __restrict__ perm,
+                                                     unsigned* __restrict__ qmax_bits, Geo g) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double invh[3] = {ihx, ihy, ihz};
-  T d[3];
-  int sp, bin;
-  particle_bin<T, P>(ion_pos, wc_pos, n_ion, i, invh, g, d, sp, bin);
-  const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
-  const int slot = atomicAdd(cursor + bin, 1);
-  sorted[slot] = T4<T>{d[0], d[1], d[2], q};
-  sidx[slot] = sp;
-  perm[slot] = (int)i;
+  unsigned qb = 0u;
+  if (i < n) {
+    const double invh[3] = {ihx, ihy, ihz};
+    T d[3];
+    int sp, bin;
+    particle_bin<T, P>(ion_pos, wc_pos, n_ion, i, invh, g, d, sp, bin);
+    const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
+    const int slot = atomicAdd(cursor + bin, 1);
+    sorted[slot] = T4<T>{d[0], d[1], d[2], q};
+    sidx[slot] = sp;
+    perm[slot] = (int)i;
+    qb = abs_q_bits(q);
+  }
+  qb = wave_max_u32(qb);
+  if ((threadIdx.x & 63) == 0) atomicMax(qmax_bits, qb);
 }
 
 // Counting sort without global atomics (used when the bins fit in LDS).
@@ -259,10 +285,14 @@ __global__ void __launch_bounds__(1024) k_bin_place(const T* __restrict__ ion_po
                                                     int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
                                                     const int* __restrict__ hist, const int* __restrict__ start,
                                                     T4<T>* __restrict__ sorted, int* __restrict__ sidx,
-                                                    int* __restrict__ perm, int chunk, Geo g) {
+                                                    int* __restrict__ perm, unsigned* __restrict__ qmax_part,
+                                                    int chunk, Geo g) {
   extern __shared__ int lc[];
+  __shared__ unsigned qm;
   for (int b = threadIdx.x; b < g.nbins; b += blockDim.x) lc[b] = 0;
+  if (threadIdx.x == 0) qm = 0u;
   __syncthreads();
+  unsigned qb = 0u;
   const double invh[3] = {ihx, ihy, ihz};
   const int64_t i0 = (int64_t)blockIdx.x * chunk;
   const int64_t i1 = min(n, i0 + chunk);
@@ -276,7 +306,12 @@ __global__ void __launch_bounds__(1024) k_bin_place(const T* __restrict__ ion_po
     sorted[slot] = T4<T>{d[0], d[1], d[2], q};
     sidx[slot] = sp;
     perm[slot] = (int)i;
+    qb = max(qb, abs_q_bits(q));
   }
+  qb = wave_max_u32(qb);
+  if ((threadIdx.x & 63) == 0) atomicMax(&qm, qb);
+  __syncthreads();
+  if (threadIdx.x == 0) qmax_part[blockIdx.x] = qm;
 }
 
 // ----------------------------------------------------------------------------
@@ -295,7 +330,7 @@ struct Ranges {
 // range (up to two per plane) is resolved by its own thread, so the block
 // waits for one round of bin_start loads instead of a chain of them.
 __device__ __forceinline__ void build_ranges(Ranges& R, const int* __restrict__ bin_start, const Geo& g,
-                                             int z_lo, int nplanes, int q_lo, int nq) {
+                                             int xsplit, int z_lo, int nplanes, int q_lo, int nq) {
   const int t = threadIdx.x;
   const int qa = wrapi(q_lo, g.NQ);
   const bool split = qa + nq > g.NQ;
@@ -307,8 +342,9 @@ __device__ __forceinline__ void build_ranges(Ranges& R, const int* __restrict__ 
     if (!split) { q0 = qa; q1 = qa + nq; }
     else if (j == 0) { q0 = qa; q1 = g.NQ; }
     else { q0 = 0; q1 = qa + nq - g.NQ; }
-    R.b[t][0] = bin_start[z * g.NQ + q0];
-    R.b[t][1] = bin_start[z * g.NQ + q1];
+    const int b0 = (xsplit * g.K[2] + z) * g.NQ;
+    R.b[t][0] = bin_start[b0 + q0];
+    R.b[t][1] = bin_start[b0 + q1];
   }
   __syncthreads();
   if (t == 0) {
@@ -335,76 +371,97 @@ __device__ __forceinline__ int range_index(const Ranges& R, int v) {
 }
 
 // ----------------------------------------------------------------------------
-// Fixed-point scale of the charge accumulators: 2^32 for FP32 plans (the
-// FP32 products are then summed exactly; |mesh charge| < 2^31), 2^40 for FP64
-// plans (rounding 2^-41 per term; |mesh charge| < 2^23).
-// c * 2^B rounded to a signed 64-bit integer.
-template <typename T>
-__device__ __forceinline__ long long to_fixed(T c) {
-  if constexpr (sizeof(T) == 4) {
-    // split c * 2^32 into floor(c) (high word) and the fraction (low word);
-    // both conversions are exact for |c| < 2^31
-    const float fl = floorf(c);
-    const float fr = (c - fl) * 4294967296.0f;   // in [0, 2^32)
-    const unsigned lo = (fr >= 4294967040.0f) ? 4294967040u : (unsigned)fr;
-    return (long long)(((unsigned long long)(long long)(int)fl << 32) | (unsigned long long)lo);
-  } else {
-    return (long long)llrint(c * 1099511627776.0);  // 2^40
-  }
+// 64-bit fixed-point charge accumulators.  FP32 plans scale every term by a
+// power of two S = 2^(30 - e), with 2^e > max |q| over the particles: a term
+// q w (|w| <= 1) becomes round(q w S), |q w S| < 2^30, one FP32 multiply and
+// one conversion to int32 whose rounding is at most 2^-31 max|q| in charge
+// units; the 64-bit sums then hold any total.  FP64 plans use S = 2^40
+// (|mesh charge| < 2^23).  Integer sums do not depend on the order of the
+// additions, so the mesh is bitwise repeatable.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float fixed_scale_fp32(unsigned qmax_bits) {
+  const float qm = __uint_as_float(qmax_bits);
+  if (!(qm > 0.0f) || !isfinite(qm)) return 1.0f;
+  int e;
+  (void)frexpf(qm, &e);  // qm < 2^e
+  return ldexpf(1.0f, 30 - e);
 }
 
+// c is the already scaled term
 template <typename T>
-__device__ __forceinline__ T from_fixed(long long v) {
-  return (T)((double)v * (sizeof(T) == 4 ? 2.3283064365386963e-10 : 9.094947017729282e-13));
+__device__ __forceinline__ long long to_fixed(T c) {
+  if constexpr (sizeof(T) == 4) return (long long)(int)rintf(c);
+  else return (long long)llrint(c);
 }
 
 // ----------------------------------------------------------------------------
 // Charge spreading into an LDS pencil (owner computes its halo), then the
 // real-to-complex transform along x.
 //
-// One workgroup owns rows y in [y0, y0+scy), z in [z0, z0+scz), all x.  It
-// visits every particle whose stencil touches those rows (its own bins and
-// the p-1 planes / one row group below) and adds only the owned part of each
-// stencil, so every mesh value is complete inside one LDS tile and no
-// workgroup writes another's rows (no global atomics, no halo buffers).
-// Accumulation is in 64-bit fixed point with integer LDS atomics: on gfx950
-// these run ~15x faster than LDS float atomics, and integer sums do not
-// depend on the order of the additions, so the mesh is bitwise repeatable.
-// After the spread the tile is converted in place to complex rows packed in
-// pairs (even row = real part, odd row = imaginary part), so one complex FFT
-// transforms two real rows; the two half spectra are then separated with the
-// Hermitian symmetry of each.
+// Tile t owns rows y in [y0, y0+scy), z in [z0, z0+scz), all x.  Its blocks
+// visit every particle whose stencil touches those rows (its own bins and the
+// p-1 planes / one row group below) and add only the owned part of each
+// stencil, so every mesh value is complete inside one LDS tile and no block
+// writes another's rows.  With nsplit > 1 the particles are further divided
+// by stencil-start column (s_x / xs); block (t, split) spreads one part and
+// writes its own partial spectrum, and the y pass adds the partial spectra in
+// split order (deterministic).  Rows carry p-1 extra columns so the stencil
+// never wraps in x inside the hot loop; the overhang is folded back before
+// the transform.  Accumulation is in 64-bit fixed point with integer LDS
+// atomics (exact, order independent).  After the spread the tile is converted
+// in place to complex rows packed in pairs (even row = real part, odd row =
+// imaginary part), so one complex FFT transforms two real rows; the two half
+// spectra are separated with the Hermitian symmetry of each.
 // ----------------------------------------------------------------------------
 template <typename T, int P>
-__global__ void __launch_bounds__(1024) k_spread_fftx(const T4<T>* __restrict__ sorted,
-                                                      const int* __restrict__ sidx,
-                                                      const int* __restrict__ bin_start,
-                                                      cpx<T>* __restrict__ spec,
-                                                      const cpx<T>* __restrict__ twg, Geo g) {
+__global__ void __launch_bounds__(512) k_spread_fftx(const T4<T>* __restrict__ sorted,
+                                                     const int* __restrict__ sidx,
+                                                     const int* __restrict__ bin_start,
+                                                     const unsigned* __restrict__ qmax_part, int nqpart,
+                                                     cpx<T>* __restrict__ spec, size_t split_stride,
+                                                     const cpx<T>* __restrict__ twg, Geo g) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2];
   const int nrows = g.scy * g.scz;
   const int nrc = nrows >> 1;
-  long long* acc = reinterpret_cast<long long*>(smem);          // [nrows][Kx]
+  constexpr int XH = P - 1;                                      // x overhang
+  const int RX = Kx + XH;                                        // accumulator row length
+  long long* acc = reinterpret_cast<long long*>(smem);          // [nrows][RX]
   cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem);               // [nrc][RS] after conversion
   const int RS = padded_len(Kx) + 1;                             // odd row stride (banks)
-  const size_t acc_bytes = (size_t)nrows * Kx * sizeof(long long);
+  const size_t acc_bytes = (size_t)nrows * RX * sizeof(long long);
   const size_t cpx_bytes = (size_t)nrc * RS * sizeof(cpx<T>);
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem + (acc_bytes > cpx_bytes ? acc_bytes : cpx_bytes));
   __shared__ Ranges R;
+  __shared__ unsigned qm_s;
 
-  const int py = blockIdx.x % g.spy, pz = blockIdx.x / g.spy;
+  const int ntiles = g.spy * g.spz;
+  const int tile_id = blockIdx.x % ntiles, split = blockIdx.x / ntiles;
+  const int py = tile_id % g.spy, pz = tile_id / g.spy;
   const int y0 = py * g.scy, z0 = pz * g.scz;
 
-  for (int e = threadIdx.x; e < nrows * Kx; e += blockDim.x) acc[e] = 0;
+  if (threadIdx.x == 0) qm_s = 0u;
+  for (int e = threadIdx.x; e < nrows * RX; e += blockDim.x) acc[e] = 0;
   copy_g2s<8>(tw, twg, g.twN);
   {
     const int nplanes = min(g.scz + P - 1, Kz);
     const int ylo = y0 - (P - 1);
-    const int q_lo = (ylo >= 0) ? (ylo >> 2) : -((3 - ylo) >> 2);
-    const int q_hi = (y0 + g.scy - 1) >> 2;
+    const int qm = (1 << g.qshift) - 1;
+    const int q_lo = (ylo >= 0) ? (ylo >> g.qshift) : -((qm - ylo) >> g.qshift);
+    const int q_hi = (y0 + g.scy - 1) >> g.qshift;
     const int nq = min(q_hi - q_lo + 1, g.NQ);
-    build_ranges(R, bin_start, g, z0 - (P - 1), nplanes, q_lo, nq);
+    build_ranges(R, bin_start, g, split, z0 - (P - 1), nplanes, q_lo, nq);  // contains barriers
+  }
+  T scale;
+  if constexpr (sizeof(T) == 4) {
+    unsigned qb = 0u;
+    for (int i = threadIdx.x; i < nqpart; i += blockDim.x) qb = max(qb, qmax_part[i]);
+    qb = wave_max_u32(qb);
+    if ((threadIdx.x & 63) == 0 && qb) atomicMax(&qm_s, qb);
+    __syncthreads();
+    scale = fixed_scale_fp32(qm_s);
+  } else {
+    scale = (T)1099511627776.0;  // 2^40
   }
 
   const int total = R.pre[R.n];
@@ -431,30 +488,34 @@ __global__ void __launch_bounds__(1024) k_spread_fftx(const T4<T>* __restrict__ 
       bspline_weights<T, P>(pt.x, wx);
       bspline_weights<T, P>(pt.y, wy);
       bspline_weights<T, P>(pt.z, wz);
+      const T qs = pt.w * scale;
 #pragma unroll
       for (int tz = 0; tz < P; ++tz) {
         int gz = sz + tz;
         if (gz >= Kz) gz -= Kz;
         const int lz = gz - z0;
         if (lz < 0 || lz >= g.scz) continue;
-        const T qz = pt.w * wz[tz];
+        const T qz = qs * wz[tz];
 #pragma unroll
         for (int ty = 0; ty < P; ++ty) {
           int gy = sy + ty;
           if (gy >= Ky) gy -= Ky;
           const int ly = gy - y0;
           if (ly < 0 || ly >= g.scy) continue;
-          unsigned long long* rp = reinterpret_cast<unsigned long long*>(acc + (size_t)(lz * g.scy + ly) * Kx);
+          unsigned long long* rp =
+              reinterpret_cast<unsigned long long*>(acc + imul(lz * g.scy + ly, RX) + sx);
           const T qyz = qz * wy[ty];
 #pragma unroll
-          for (int tx = 0; tx < P; ++tx) {
-            int gx = sx + tx;
-            if (gx >= Kx) gx -= Kx;
-            atomicAdd(rp + gx, (unsigned long long)to_fixed<T>(qyz * wx[tx]));
-          }
+          for (int tx = 0; tx < P; ++tx) atomicAdd(rp + tx, (unsigned long long)to_fixed<T>(qyz * wx[tx]));
         }
       }
     }
+  }
+  __syncthreads();
+  // fold the x overhang of every row back to the row start (periodic in x)
+  for (int e = threadIdx.x; e < nrows * XH; e += blockDim.x) {
+    const int row = e / XH, j = e - row * XH;
+    acc[imul(row, RX) + j] += acc[imul(row, RX) + Kx + j];
   }
   __syncthreads();
 
@@ -464,19 +525,21 @@ __global__ void __launch_bounds__(1024) k_spread_fftx(const T4<T>* __restrict__ 
     constexpr int kMaxPer = 16;
     long long v[kMaxPer];
     const int per = (nrows * Kx + blockDim.x - 1) / blockDim.x;
+    const int lkx = 31 - __clz(Kx);
 #pragma unroll
     for (int c = 0; c < kMaxPer; ++c) {
       const int e = threadIdx.x + c * blockDim.x;
-      if (c < per && e < nrows * Kx) v[c] = acc[e];
+      if (c < per && e < nrows * Kx) v[c] = acc[imul(e >> lkx, RX) + (e & (Kx - 1))];
     }
     __syncthreads();
+    const double inv_scale = 1.0 / (double)scale;
     T* out = reinterpret_cast<T*>(tile);
 #pragma unroll
     for (int c = 0; c < kMaxPer; ++c) {
       const int e = threadIdx.x + c * blockDim.x;
       if (c < per && e < nrows * Kx) {
-        const int row = e / Kx, x = e - row * Kx;
-        out[2 * ((row >> 1) * RS + lds_pad(x)) + (row & 1)] = from_fixed<T>(v[c]);
+        const int row = e >> lkx, x = e & (Kx - 1);
+        out[2 * (imul(row >> 1, RS) + lds_pad(x)) + (row & 1)] = (T)((double)v[c] * inv_scale);
       }
     }
     __syncthreads();
@@ -485,13 +548,14 @@ __global__ void __launch_bounds__(1024) k_spread_fftx(const T4<T>* __restrict__ 
   fft_rows<T, false, kEPT, true>(tile, nrc, Kx, RS, 1, false, tw, g.twN);
 
   const int Kh = g.Kh;
+  cpx<T>* sp_out = spec + (size_t)split * split_stride;
   for (int e = threadIdx.x; e < nrows * Kh; e += blockDim.x) {
     const int ly = e % g.scy;
     const int rest = e / g.scy;
     const int lz = rest % g.scz;
     const int k = rest / g.scz;
     const int row = lz * g.scy + ly;
-    const cpx<T>* zr = tile + (row >> 1) * RS;
+    const cpx<T>* zr = tile + imul(row >> 1, RS);
     const cpx<T> z1 = zr[lds_pad(k)];
     const cpx<T> z2 = cconj(zr[lds_pad((Kx - k) & (Kx - 1))]);
     cpx<T> out;
@@ -501,13 +565,190 @@ __global__ void __launch_bounds__(1024) k_spread_fftx(const T4<T>* __restrict__ 
       const cpx<T> d = csub(z1, z2);
       out = cpx<T>{(T)0.5 * d.y, (T)-0.5 * d.x};
     }
-    spec[((size_t)k * Kz + (z0 + lz)) * Ky + (y0 + ly)] = out;
+    sp_out[(unsigned)imul(imul(k, Kz) + z0 + lz, Ky) + (y0 + ly)] = out;
   }
 }
 
 // ----------------------------------------------------------------------------
+// Plane spread with both forward in-plane transforms (used when one z plane
+// fits in LDS).  Block (z, split) owns mesh plane z and visits every particle
+// whose stencil-start plane is one of z-p+1 .. z (and whose stencil-start
+// column is in its x split); each visit adds the particle's p x p points of
+// that plane with the single z weight of the plane.  With no halo in x or y
+// every visit does the same work, and no per-row ownership tests are needed.
+// The plane is then converted to complex row pairs, transformed along x
+// (real-to-complex, two rows per complex FFT), rearranged to [kx][y] and
+// transformed along y, and written as spec[kx][z][y] (one partial spectrum
+// per x split; the z pass adds them in split order).
+// ----------------------------------------------------------------------------
+template <typename T, int P>
+__global__ void __launch_bounds__(1024) k_spread_xy(const T4<T>* __restrict__ sorted,
+                                                    const int* __restrict__ sidx,
+                                                    const int* __restrict__ bin_start,
+                                                    const unsigned* __restrict__ qmax_part, int nqpart,
+                                                    cpx<T>* __restrict__ spec, size_t split_stride,
+                                                    const cpx<T>* __restrict__ twg, Geo g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2], Kh = g.Kh;
+  constexpr int XH = P - 1;
+  const int RX = Kx + XH;
+  const int RS = padded_len(Kx) + 1;  // x-transform rows (complex pairs of real rows)
+  const int RY = padded_len(Ky) + 1;  // y-transform rows ([kx][y])
+  long long* acc = reinterpret_cast<long long*>(smem);  // [Ky][RX]
+  cpx<T>* tx_tile = reinterpret_cast<cpx<T>*>(smem);    // [Ky/2][RS]
+  cpx<T>* ty_tile = reinterpret_cast<cpx<T>*>(smem);    // [Kh][RY]
+  const size_t b_acc = (size_t)Ky * RX * sizeof(long long);
+  const size_t b_tx = (size_t)(Ky / 2) * RS * sizeof(cpx<T>);
+  const size_t b_ty = (size_t)Kh * RY * sizeof(cpx<T>);
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem + max(b_acc, max(b_tx, b_ty)));
+  __shared__ Ranges R;
+  __shared__ unsigned qm_s;
+
+  const int z = blockIdx.x % Kz, split = blockIdx.x / Kz;
+  if (threadIdx.x == 0) qm_s = 0u;
+  for (int e = threadIdx.x; e < Ky * RX; e += blockDim.x) acc[e] = 0;
+  copy_g2s<8>(tw, twg, g.twN);
+  build_ranges(R, bin_start, g, split, z - (P - 1), min(P, Kz), 0, g.NQ);  // contains barriers
+  T scale;
+  if constexpr (sizeof(T) == 4) {
+    unsigned qb = 0u;
+    for (int i = threadIdx.x; i < nqpart; i += blockDim.x) qb = max(qb, qmax_part[i]);
+    qb = wave_max_u32(qb);
+    if ((threadIdx.x & 63) == 0 && qb) atomicMax(&qm_s, qb);
+    __syncthreads();
+    scale = fixed_scale_fp32(qm_s);
+  } else {
+    scale = (T)1099511627776.0;  // 2^40
+  }
+
+  const int total = R.pre[R.n];
+  constexpr int PB = 2;  // particles fetched per thread before processing
+  for (int v0 = threadIdx.x; v0 < total; v0 += PB * blockDim.x) {
+    T4<T> pts[PB];
+    int sps[PB];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const int v = v0 + u * blockDim.x;
+      if (v < total) {
+        const int idx = range_index(R, v);
+        pts[u] = sorted[idx];
+        sps[u] = sidx[idx];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      if (v0 + u * blockDim.x >= total) continue;
+      const T4<T> pt = pts[u];
+      const int sp = sps[u];
+      const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
+      int tz = z - sz;
+      if (tz < 0) tz += Kz;
+      T wx[P], wy[P], wz[P];
+      bspline_weights<T, P>(pt.x, wx);
+      bspline_weights<T, P>(pt.y, wy);
+      bspline_weights<T, P>(pt.z, wz);
+      T wzt = wz[0];
+#pragma unroll
+      for (int q = 1; q < P; ++q) wzt = (tz == q) ? wz[q] : wzt;
+      const T qz = pt.w * scale * wzt;
+#pragma unroll
+      for (int ty = 0; ty < P; ++ty) {
+        int gy = sy + ty;
+        if (gy >= Ky) gy -= Ky;
+        unsigned long long* rp = reinterpret_cast<unsigned long long*>(acc + imul(gy, RX) + sx);
+        const T qyz = qz * wy[ty];
+#pragma unroll
+        for (int tx = 0; tx < P; ++tx) atomicAdd(rp + tx, (unsigned long long)to_fixed<T>(qyz * wx[tx]));
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < Ky * XH; e += blockDim.x) {
+    const int row = e / XH, j = e - row * XH;
+    acc[imul(row, RX) + j] += acc[imul(row, RX) + Kx + j];
+  }
+  __syncthreads();
+
+  // fixed point -> complex row pairs (in place through registers)
+  const int lkx = 31 - __clz(Kx), lky = 31 - __clz(Ky);
+  {
+    constexpr int kMaxPer = 16;
+    long long v[kMaxPer];
+#pragma unroll
+    for (int c = 0; c < kMaxPer; ++c) {
+      const int e = threadIdx.x + c * blockDim.x;
+      if (e < Ky * Kx) v[c] = acc[imul(e >> lkx, RX) + (e & (Kx - 1))];
+    }
+    __syncthreads();
+    const double inv_scale = 1.0 / (double)scale;
+    T* out = reinterpret_cast<T*>(tx_tile);
+#pragma unroll
+    for (int c = 0; c < kMaxPer; ++c) {
+      const int e = threadIdx.x + c * blockDim.x;
+      if (e < Ky * Kx) {
+        const int row = e >> lkx, x = e & (Kx - 1);
+        out[2 * (imul(row >> 1, RS) + lds_pad(x)) + (row & 1)] = (T)((double)v[c] * inv_scale);
+      }
+    }
+    __syncthreads();
+  }
+  fft_rows<T, false, kEPT, true>(tx_tile, Ky / 2, Kx, RS, 1, false, tw, g.twN);
+
+  // separate the two half spectra of every row pair into [kx][y] rows
+  {
+    constexpr int kMaxOut = 16;
+    cpx<T> o[kMaxOut];
+#pragma unroll
+    for (int c = 0; c < kMaxOut; ++c) {
+      const int e = threadIdx.x + c * blockDim.x;  // e = kx * Ky + y
+      if (e < Kh * Ky) {
+        const int k = e >> lky, y = e & (Ky - 1);
+        const cpx<T>* zr = tx_tile + imul(y >> 1, RS);
+        const cpx<T> z1 = zr[lds_pad(k)];
+        const cpx<T> z2 = cconj(zr[lds_pad((Kx - k) & (Kx - 1))]);
+        if ((y & 1) == 0) {
+          o[c] = cpx<T>{(T)0.5 * (z1.x + z2.x), (T)0.5 * (z1.y + z2.y)};
+        } else {
+          const cpx<T> d = csub(z1, z2);
+          o[c] = cpx<T>{(T)0.5 * d.y, (T)-0.5 * d.x};
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kMaxOut; ++c) {
+      const int e = threadIdx.x + c * blockDim.x;
+      if (e < Kh * Ky) {
+        const int k = e >> lky, y = e & (Ky - 1);
+        ty_tile[imul(k, RY) + lds_pad(y)] = o[c];
+      }
+    }
+    __syncthreads();
+  }
+  fft_rows<T, false, kEPT, true>(ty_tile, Kh, Ky, RY, 1, false, tw, g.twN);
+
+  cpx<T>* out = spec + (size_t)split * split_stride;
+  for (int e = threadIdx.x; e < Kh * Ky; e += blockDim.x) {
+    const int k = e >> lky, y = e & (Ky - 1);
+    out[(unsigned)imul(imul(k, Kz) + z, Ky) + y] = ty_tile[imul(k, RY) + lds_pad(y)];
+  }
+}
+
+// Sum of the partial spectra of the x splits in split order (inspection copy).
+template <typename T>
+__global__ void k_sum_partials(cpx<T>* __restrict__ dst, const cpx<T>* __restrict__ src, int nsum, size_t stride,
+                               size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cpx<T> a = src[i];
+  for (int s = 1; s < nsum; ++s) a = cadd(a, src[(size_t)s * stride + i]);
+  dst[i] = a;
+}
+
+// ----------------------------------------------------------------------------
 // Transforms along y of contiguous blocks of zb rows (forward on the charge
-// spectrum, inverse on the three field spectra).
+// spectrum, after adding the partial spectra of the x splits; inverse on the
+// three field spectra).
 // Used forward on spec and inverse on the three field spectra.
 // ----------------------------------------------------------------------------
 // Final FP64 reduction of the z-pass partials with a fixed tree (bitwise
@@ -537,6 +778,7 @@ __device__ void reduce_partials(const double* __restrict__ partials, int nblk, d
 
 template <typename T, bool INV>
 __global__ void __launch_bounds__(256) k_ffty(cpx<T>* __restrict__ data, const cpx<T>* __restrict__ twg, Geo g,
+                                              int nsum, size_t sum_stride,
                                               const double* __restrict__ partials, double pre,
                                               double* __restrict__ energy, double* __restrict__ virial) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -555,16 +797,25 @@ __global__ void __launch_bounds__(256) k_ffty(cpx<T>* __restrict__ data, const c
       const int e = b0 + u * blockDim.x;
       if (e < n) r[u] = base[e];
     }
+    // partial spectra of the other x splits, added in split order
+    for (int sp = 1; sp < nsum; ++sp) {
+      const cpx<T>* ps = base + (size_t)sp * sum_stride;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = b0 + u * blockDim.x;
+        if (e < n) r[u] = cadd(r[u], ps[e]);
+      }
+    }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int e = b0 + u * blockDim.x;
-      if (e < n) buf[(e >> lky) * RS + lds_pad(e & (Ky - 1))] = r[u];
+      if (e < n) buf[imul(e >> lky, RS) + lds_pad(e & (Ky - 1))] = r[u];
     }
   }
   copy_g2s<8>(tw, twg, g.twN);
   __syncthreads();
   fft_rows<T, INV, kEPT, true>(buf, g.zb, Ky, RS, 1, false, tw, g.twN);
-  for (int e = threadIdx.x; e < n; e += blockDim.x) base[e] = buf[(e >> lky) * RS + lds_pad(e & (Ky - 1))];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) base[e] = buf[imul(e >> lky, RS) + lds_pad(e & (Ky - 1))];
   if (INV && energy && blockIdx.x == 0) {
     __syncthreads();
     reduce_partials(partials, g.nzblk, pre, energy, virial, reinterpret_cast<double*>(smem));
@@ -583,7 +834,8 @@ __global__ void __launch_bounds__(256) k_ffty(cpx<T>* __restrict__ data, const c
 //   component cancel in +-n pairs).
 // ----------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict__ spec, cpx<T>* __restrict__ fspec,
+__global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict__ spec, int nsum, size_t sum_stride,
+                                                       cpx<T>* __restrict__ fspec,
                                                        const double* __restrict__ G, double* __restrict__ partials,
                                                        const cpx<T>* __restrict__ twg, Geo g, PoissonConsts pc) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -593,19 +845,31 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
   cpx<T>* tw = buf + Kz * w3;
   __shared__ double red[16][8];
 
-  const int nyb = Ky / yb;
-  const int kx = blockIdx.x / nyb, y0 = (blockIdx.x % nyb) * yb;
-  for (int base = threadIdx.x; base < Kz * yb; base += 8 * blockDim.x) {
+  const int lyb = 31 - __clz(yb);  // yb is a power of two
+  const int nyb = Ky >> lyb;
+  const int kx = blockIdx.x / nyb, y0 = (blockIdx.x - kx * nyb) << lyb;
+  const unsigned col0 = (unsigned)imul(imul(kx, Kz), Ky) + y0;  // spec[kx][0][y0]
+  const int n = Kz << lyb;                                      // elements (z, yl), yl fastest
+  for (int base = threadIdx.x; base < n; base += 8 * blockDim.x) {
     cpx<T> r[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = base + u * blockDim.x;
-      if (e < Kz * yb) r[u] = spec[((size_t)kx * Kz + e / yb) * Ky + y0 + e % yb];
+      if (e < n) r[u] = spec[col0 + imul(e >> lyb, Ky) + (e & (yb - 1))];
+    }
+    // partial spectra of the other x splits, added in split order
+    for (int sp = 1; sp < nsum; ++sp) {
+      const cpx<T>* ps = spec + (size_t)sp * sum_stride;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * blockDim.x;
+        if (e < n) r[u] = cadd(r[u], ps[col0 + imul(e >> lyb, Ky) + (e & (yb - 1))]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = base + u * blockDim.x;
-      if (e < Kz * yb) buf[(e / yb) * w3 + e % yb] = r[u];
+      if (e < n) buf[imul(e >> lyb, w3) + (e & (yb - 1))] = r[u];
     }
   }
   copy_g2s<8>(tw, twg, g.twN);
@@ -617,28 +881,29 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
   const double wgt = (kx == 0 || kx == Kx / 2) ? 1.0 : 2.0;
   const double kxv = pc.two_pi_over_L[0] * kx;
   const double kxd = (kx == Kx / 2) ? 0.0 : kxv;
-  for (int base = threadIdx.x; base < Kz * yb; base += 8 * blockDim.x) {
+  for (int base = threadIdx.x; base < n; base += 8 * blockDim.x) {
     double Gr[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = base + u * blockDim.x;
-      if (e < Kz * yb) {
-        const int yl = e % yb, z = e / yb, ny = y0 + yl;
-        Gr[u] = G[((size_t)kx * Kyh + min(ny, Ky - ny)) * Kzh + min(z, Kz - z)];
+      if (e < n) {
+        const int yl = e & (yb - 1), z = e >> lyb, ny = y0 + yl;
+        Gr[u] = G[(unsigned)imul(imul(kx, Kyh) + min(ny, Ky - ny), Kzh) + min(z, Kz - z)];
       }
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = base + u * blockDim.x;
-      if (e >= Kz * yb) continue;
-      const int yl = e % yb, z = e / yb;
+      if (e >= n) continue;
+      const int yl = e & (yb - 1), z = e >> lyb;
       const int ny = y0 + yl;
       const double kyv = pc.two_pi_over_L[1] * (ny <= Ky / 2 ? ny : ny - Ky);
       const double kzv = pc.two_pi_over_L[2] * (z <= Kz / 2 ? z : z - Kz);
       const double kyd = (2 * ny == Ky) ? 0.0 : kyv;
       const double kzd = (2 * z == Kz) ? 0.0 : kzv;
       const double Gv = Gr[u];
-      const cpx<T> q = buf[z * w3 + yl];
+      cpx<T>* bz = buf + imul(z, w3) + yl;
+      const cpx<T> q = bz[0];
       const double s2 = (double)q.x * (double)q.x + (double)q.y * (double)q.y;
       const double t = wgt * Gv * s2;
       const double k2 = kxv * kxv + kyv * kyv + kzv * kzv;
@@ -652,17 +917,19 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
       acc[6] += t * (-c * kyd * kzd);
       // -i k' G Q^ = k' G (q.y, -q.x)
       const T gx = (T)(Gv * kxd), gy = (T)(Gv * kyd), gz = (T)(Gv * kzd);
-      buf[z * w3 + yl] = cpx<T>{gx * q.y, -gx * q.x};
-      buf[z * w3 + yb + yl] = cpx<T>{gy * q.y, -gy * q.x};
-      buf[z * w3 + 2 * yb + yl] = cpx<T>{gz * q.y, -gz * q.x};
+      bz[0] = cpx<T>{gx * q.y, -gx * q.x};
+      bz[yb] = cpx<T>{gy * q.y, -gy * q.x};
+      bz[2 * yb] = cpx<T>{gz * q.y, -gz * q.x};
     }
   }
   __syncthreads();
   fft_rows<T, true, kEPT>(buf, w3, Kz, 1, w3, true, tw, g.twN);
-  for (int e = threadIdx.x; e < Kz * w3; e += blockDim.x) {
-    const int c = e % w3, z = e / w3;
-    const int a = c / yb, yl = c % yb;
-    fspec[(((size_t)a * Kh + kx) * Kz + z) * Ky + y0 + yl] = buf[z * w3 + c];
+  // store: e = ((z * 3 + a) << lyb) + yl
+  const unsigned fstride = (unsigned)imul(imul(Kh, Kz), Ky);
+  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
+    const int za = e >> lyb, yl = e & (yb - 1);
+    const int z = za / 3, a = za - 3 * z;
+    fspec[a * fstride + col0 + imul(z, Ky) + yl] = buf[imul(z, w3) + imul(a, yb) + yl];
   }
 
   // deterministic block reduction of the 7 FP64 partial sums
@@ -689,6 +956,10 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
 // real fields interleaved, E[z][y][x] = (Ex, Ey, Ez), so the gather reads one
 // 3-component record per stencil point.
 // ----------------------------------------------------------------------------
+#ifndef DPLR_GATHER_OCC
+#define DPLR_GATHER_OCC
+#endif
+
 template <typename T>
 struct F3 {
   T x, y, z;
@@ -715,7 +986,7 @@ __global__ void __launch_bounds__(512) k_ifftx(const cpx<T>* __restrict__ fspec,
     const int r0 = 2 * c_t, r1 = r0 + 1;
     const cpx<T>* s0 = fspec + (size_t)(r0 / yb) * fstride + (size_t)z * Ky + y0 + r0 % yb;
     const cpx<T>* s1 = fspec + (size_t)(r1 / yb) * fstride + (size_t)z * Ky + y0 + r1 % yb;
-    cpx<T>* zr = tile + (size_t)c_t * RS;
+    cpx<T>* zr = tile + imul(c_t, RS);
     for (int kb = k_t; kb < Kh; kb += 4 * kstep) {
       cpx<T> A[4], B[4];
 #pragma unroll
@@ -749,7 +1020,7 @@ __global__ void __launch_bounds__(512) k_ifftx(const cpx<T>* __restrict__ fspec,
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int r = a * yb + yl;
-      v[a] = tr[2 * (size_t)(r >> 1) * RS + col + (r & 1)];
+      v[a] = tr[2 * imul(r >> 1, RS) + col + (r & 1)];
     }
     out[e] = F3<T>{v[0], v[1], v[2]};
   }
@@ -764,7 +1035,7 @@ __global__ void __launch_bounds__(512) k_ifftx(const cpx<T>* __restrict__ fspec,
 // mapped to the same XCD so each XCD's L2 serves one slab of the field.
 // ----------------------------------------------------------------------------
 template <typename T, int P>
-__global__ void __launch_bounds__(256) k_gather(const F3<T>* __restrict__ field, const T4<T>* __restrict__ sorted,
+__global__ void __launch_bounds__(256) DPLR_GATHER_OCC k_gather(const F3<T>* __restrict__ field, const T4<T>* __restrict__ sorted,
                                                 const int* __restrict__ sidx, const int* __restrict__ perm,
                                                 int n, int nchunks, T* __restrict__ ion_f, T* __restrict__ wc_f,
                                                 int64_t n_ion, T fscale, int accumulate, int nxcd, Geo g) {
@@ -799,23 +1070,37 @@ __global__ void __launch_bounds__(256) k_gather(const F3<T>* __restrict__ field,
     for (int q = 1; q < P; ++q) wxt = (tx == q) ? wx[q] : wxt;
     int gx = sx + tx;
     if (gx >= Kx) gx -= Kx;
+    // all loads of a batch of z planes are issued before any of them is used
+    // (memory-level parallelism: the loop is latency bound otherwise)
+    constexpr int TZB = (P <= 5) ? P : ((P <= 6) ? 3 : 2);
 #pragma unroll
-    for (int tz = 0; tz < P; ++tz) {
-      int gz = sz + tz;
-      if (gz >= Kz) gz -= Kz;
-      F3<T> r[P];
+    for (int tz0 = 0; tz0 < P; tz0 += TZB) {
+      F3<T> r[TZB][P];
 #pragma unroll
-      for (int ty = 0; ty < P; ++ty) {
-        int gy = sy + ty;
-        if (gy >= Ky) gy -= Ky;
-        r[ty] = field[((size_t)gz * Ky + gy) * Kx + gx];
+      for (int dz = 0; dz < TZB; ++dz) {
+        if (tz0 + dz < P) {
+          int gz = sz + tz0 + dz;
+          if (gz >= Kz) gz -= Kz;
+          const F3<T>* fz = field + (unsigned)imul(gz, Ky) * (unsigned)Kx + gx;
+#pragma unroll
+          for (int ty = 0; ty < P; ++ty) {
+            int gy = sy + ty;
+            if (gy >= Ky) gy -= Ky;
+            r[dz][ty] = fz[imul(gy, Kx)];
+          }
+        }
       }
 #pragma unroll
-      for (int ty = 0; ty < P; ++ty) {
-        const T w = wz[tz] * wy[ty];
-        part[0] += w * r[ty].x;
-        part[1] += w * r[ty].y;
-        part[2] += w * r[ty].z;
+      for (int dz = 0; dz < TZB; ++dz) {
+        if (tz0 + dz < P) {
+#pragma unroll
+          for (int ty = 0; ty < P; ++ty) {
+            const T w = wz[tz0 + dz] * wy[ty];
+            part[0] += w * r[dz][ty].x;
+            part[1] += w * r[dz][ty].y;
+            part[2] += w * r[dz][ty].z;
+          }
+        }
       }
     }
     qw = fscale * pt.w * wxt;
