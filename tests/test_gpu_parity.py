@@ -123,12 +123,13 @@ def test_fp64_refined_matches_ewald_1e9(torch_dev, ewald):
 
 
 # FP32 bar against the FP64 oracle at identical (FP32-rounded) inputs: the
-# spread sums FP32 products exactly, so the error comes from FP32 rounding in
-# the B-spline weights and products (~1e-7 relative each), the three FFT
-# passes (~eps * log2(K^3) ~ 1e-6 of the largest mode) and the 125-term
-# gather; water's near-cancelling intramolecular forces amplify relative
-# force error ~10x over the mesh error.  Bar: 1e-5 relative force RMSE,
-# 2e-6 relative energy and virial (largest virial component / |E|).
+# spread rounds each FP32 product to a fixed-point quantum of at most
+# 2^-31 max|q| and sums exactly, so the error comes from FP32 rounding in the
+# B-spline weights and products (~1e-7 relative each), the three FFT passes
+# (~eps * log2(K^3) ~ 1e-6 of the largest mode) and the 125-term gather;
+# water's near-cancelling intramolecular forces amplify relative force error
+# ~10x over the mesh error.  Bar: 1e-5 relative force RMSE, 2e-6 relative
+# energy and virial (largest virial component / |E|).
 FP32_TOL_F, FP32_TOL_E = 1e-5, 2e-6
 
 
@@ -157,3 +158,53 @@ def test_zero_net_force_and_mesh_shift(torch_dev):
     # the rounding of r + shift leave ~1e-12 differences
     assert abs(E2 - E) <= 1e-10 * abs(E)
     assert np.abs(np.concatenate([fi2, fw2]) - F).max() <= 1e-10 * np.abs(F).max()
+
+
+# Pencil-tile spread (meshes whose z planes do not fit in LDS: Kx * Ky > 16384)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pencil_tile_path_matches_pppm_oracle(torch_dev, precision):
+    s = systems.workload(1).system()
+    tol = 1e-10 if precision == "fp64" else FP32_TOL_F
+    tole = 1e-10 if precision == "fp64" else FP32_TOL_E
+    check_vs_pppm(torch_dev, s, (256, 128, 16), 5, precision, tol, tole, tole)
+
+
+# ---------------------------------------------------------------------------
+# The 216,576-atom system (72,192 waters + 72,192 WCs, 129.3 A, 128^3) in the
+# plan configuration the benchmark times: every force against the FP64 PPPM
+# oracle, and sampled forces against the stored FP64 Ewald values.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def big():
+    return systems.workload(3).system()
+
+
+@pytest.fixture(scope="module")
+def big_gold():
+    import json, os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ewald_water72192_fp32.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def test_full_size_fp32_matches_pppm_oracle(torch_dev, big):
+    check_vs_pppm(torch_dev, big, 128, 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
+
+
+def test_full_size_coarse_mesh_fp32_matches_pppm_oracle(torch_dev, big):
+    # the coarse mesh of the learned form (x-split partial spectra: 8 splits)
+    check_vs_pppm(torch_dev, big, 64, 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
+
+
+@pytest.mark.parametrize("order,bound", [(5, 2e-3), (8, 1e-4)])
+def test_full_size_against_ewald(torch_dev, big, big_gold, order, bound):
+    """Method error of FP32 PPPM at 128^3 against FP64 Ewald on 2,048 sampled
+    forces: order 8 meets the 1e-4 relative force RMSE target; order 5 is
+    held to its measured level (1.5e-3) as a regression bound."""
+    E, fi, fw, W, _ = run_gpu(torch_dev, big, 128, order, "fp32")
+    F = np.concatenate([fi, fw])[np.array(big_gold["sample_index"])]
+    F0 = np.array(big_gold["sample_force"])
+    err, errE = rel(F, F0), abs(E - big_gold["energy"]) / abs(big_gold["energy"])
+    print(f"order {order} vs Ewald: dF={err:.3e} dE={errE:.3e}")
+    assert err <= bound
+    assert errE <= bound
