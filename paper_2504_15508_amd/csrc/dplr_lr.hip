@@ -173,6 +173,7 @@ bool choose_geometry(dplr_lr_plan p) {
   g.K[0] = Kx; g.K[1] = Ky; g.K[2] = Kz;
   g.Kh = Kx / 2 + 1;
   g.qshift = 2;
+  g.split_by_index = 0;
   g.NQ = Ky >> g.qshift;
   g.twN = std::max(Kx, std::max(Ky, Kz));
   const size_t twb = g.twN * cs;
@@ -195,6 +196,9 @@ bool choose_geometry(dplr_lr_plan p) {
       g.nsplit = 1;
       while (Kz * g.nsplit < target && g.nsplit < DPLR_SPREAD_MAX_SPLIT && Kx / (2 * g.nsplit) >= 4) g.nsplit *= 2;
       g.xs = Kx / g.nsplit;
+      // particles are split by index parity: each split still covers the
+      // whole plane, so its LDS atomics spread over every row and column
+      g.split_by_index = 1;
       // a plane visits all row groups of its planes: coarse groups keep the
       // sort small while consecutive particles stay close in y
       g.qshift = std::min(4, 31 - __builtin_clz((unsigned)Ky));
@@ -525,7 +529,7 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
   DPLR_ALLOC(p->sorted, 4 * ts * cap, "sorted");
   DPLR_ALLOC(p->perm, sizeof(int) * cap, "perm");
   DPLR_ALLOC(p->sidx, sizeof(int) * cap, "stencil starts");
-  DPLR_ALLOC(p->spec, cs * nspec * g.nsplit, "spectrum (one partial per x split)");
+  DPLR_ALLOC(p->spec, cs * nspec * g.nsplit, "spectrum (one partial per particle split)");
   DPLR_ALLOC(p->qmax, sizeof(unsigned) * (size_t)std::max(p->max_chunks, 1), "charge maxima");
   DPLR_ALLOC(p->fspec, 3 * cs * nspec, "field spectra");
   DPLR_ALLOC(p->field, 3 * ts * (size_t)g.K[0] * g.K[1] * g.K[2], "fields");
@@ -691,7 +695,7 @@ dplr_lr_status dplr_lr_debug_copy(dplr_lr_plan p, int32_t which, void* dst, int6
   if (!dst || bytes < 0 || bytes > size) return fail(p, DPLR_LR_E_INVALID, "bad destination or size");
   const void* src = which == DPLR_LR_BUF_SPECTRUM ? p->spec : which == DPLR_LR_BUF_INFLUENCE ? (const void*)p->G : p->fspec;
   if (which == DPLR_LR_BUF_SPECTRUM && p->plane && p->geo.nsplit > 1) {
-    // the plane spread leaves one partial spectrum per x split: report their sum
+    // the plane spread leaves one partial spectrum per particle split: report their sum
     const size_t cs = 2 * p->tsize;
     if ((size_t)bytes % cs) return fail(p, DPLR_LR_E_INVALID, "size must be a whole number of complex values");
     const size_t n = (size_t)bytes / cs, nspec = (size_t)size / cs;

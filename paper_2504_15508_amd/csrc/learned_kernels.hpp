@@ -47,25 +47,6 @@ __device__ __forceinline__ float dsilu(float z) {
   return s * (1.0f + z * (1.0f - s));
 }
 
-// acc (32 x 32) += A (32 x K) * B (K x 32) on one wave with
-// v_mfma_f32_32x32x8_bf16_1k.  Operands are bf16 in LDS addressed as
-// A(m, k) = A[m * sam + k * sak] and B(k, n) = B[k * sbk + n * sbn].
-// Lane l supplies A(l % 32, 4 (l / 32) + i) and B(4 (l / 32) + i, l % 32).
-__device__ __forceinline__ void mfma_tile(f32x16& acc, const unsigned short* A, int sam, int sak,
-                                          const unsigned short* B, int sbk, int sbn, int K) {
-  const int l = threadIdx.x & 63;
-  const int mn = l & 31, kh = (l >> 5) * 4;
-  for (int k0 = 0; k0 < K; k0 += 8) {
-    bf16x4 a, b;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      a[i] = (short)A[mn * sam + (k0 + kh + i) * sak];
-      b[i] = (short)B[(k0 + kh + i) * sbk + mn * sbn];
-    }
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-  }
-}
-
 // row / column of accumulator register r of this lane in the 32 x 32 tile
 __device__ __forceinline__ int acc_row(int r) { return 8 * (r >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (r & 3); }
 __device__ __forceinline__ int acc_col() { return threadIdx.x & 31; }
@@ -125,26 +106,81 @@ __global__ void k_cell_scatter(const float* __restrict__ ion_pos, const float* _
 }
 
 // ---------------------------------------------------------------------------
-// Descriptor: one thread per (cell-sorted) particle.  Writes T [n][128] (FP32,
-// index 4k + a) and the normalised MLP input x [n][128] (bf16).
+// Descriptor: four lanes per (cell-sorted) particle.  Lane g owns the radial
+// orders k = g, g+4, ..., g+28, advanced with the stride-4 Chebyshev
+// recurrence T_{k+4} = 2 T_4 T_k - T_{k-4}, so a lane holds 8 x 4
+// accumulators instead of 32 x 4 (high occupancy hides the memory latency of
+// the neighbour scan).  Two phases: the four lanes scan the 27 neighbour cells
+// together (candidate jb + g), and the ones inside the cutoff are appended to
+// the particle's LDS list in candidate order (ballot + prefix count, so the
+// order is deterministic); then every lane accumulates its orders over the
+// whole list.  Writes T [n][128] (FP32, index 4k + a) and the normalised MLP
+// input x [n][128] (bf16).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(128) k_descriptor(const float4* __restrict__ cpos, const int* __restrict__ start,
-                                                    int n, const float* __restrict__ params,
-                                                    float* __restrict__ Tout, unsigned short* __restrict__ X,
-                                                    CellGeo c) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+constexpr int kDescLanes = 4;
+constexpr int kDescThreads = 256;
+constexpr int kDescParts = kDescThreads / kDescLanes;
+constexpr int kNbrMax = 64;
+
+__device__ __forceinline__ void accumulate_pairs(float (&T)[8][4], const float4 pi, const float4* __restrict__ cpos,
+                                                 const int* list, int cnt, int g, const CellGeo& c) {
+  const float inv_rc = 1.0f / c.rc;
+  for (int t = 0; t < cnt; ++t) {
+    const float4 pj = cpos[list[t]];
+    float d0 = pj.x - pi.x, d1 = pj.y - pi.y, d2 = pj.z - pi.z;
+    d0 -= c.L[0] * rintf(d0 * c.invL[0]);
+    d1 -= c.L[1] * rintf(d1 * c.invL[1]);
+    d2 -= c.L[2] * rintf(d2 * c.invL[2]);
+    const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const float r = sqrtf(r2), ir = 1.0f / r;
+    const float sw = 0.5f * (1.0f + __cosf(3.14159265358979f * r * inv_rc));
+    const float x = 2.0f * r * inv_rc - 1.0f;
+    const float w = pj.w * sw;
+    const float u1 = d0 * ir, u2 = d1 * ir, u3 = d2 * ir;
+    const float t2 = 2.0f * x * x - 1.0f, t3 = 2.0f * x * t2 - x, t4 = 2.0f * x * t3 - t2;
+    // lane g starts from T_g and T_{4-g}
+    float cur = (g == 0) ? 1.0f : (g == 1) ? x : (g == 2) ? t2 : t3;
+    float prev = (g == 0) ? t4 : (g == 1) ? t3 : (g == 2) ? t2 : x;
+    const float t4x2 = 2.0f * t4;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      if (m > 0) {
+        const float nxt = t4x2 * cur - prev;
+        prev = cur;
+        cur = nxt;
+      }
+      const float wg = w * cur;
+      T[m][0] += wg;
+      T[m][1] += wg * u1;
+      T[m][2] += wg * u2;
+      T[m][3] += wg * u3;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kDescThreads) k_descriptor(const float4* __restrict__ cpos,
+                                                             const int* __restrict__ start, int n,
+                                                             const float* __restrict__ params,
+                                                             float* __restrict__ Tout,
+                                                             unsigned short* __restrict__ X, CellGeo c) {
+  __shared__ int lists[kDescParts][kNbrMax];
+  const int g = threadIdx.x & (kDescLanes - 1), p = threadIdx.x / kDescLanes;
+  const int lane = threadIdx.x & 63, gbase = lane & ~(kDescLanes - 1);
+  const int i = blockIdx.x * kDescParts + p;
+  if (i >= n) return;  // the four lanes of a particle leave together
+  int* list = lists[p];
   const float4 pi = cpos[i];
-  float T[32][4];
+  float T[8][4];
 #pragma unroll
-  for (int k = 0; k < 32; ++k) {
+  for (int m = 0; m < 8; ++m) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) T[k][a] = 0.0f;
+    for (int a = 0; a < 4; ++a) T[m][a] = 0.0f;
   }
   const int cx = min((int)(pi.x * c.cinv[0]), c.nc[0] - 1);
   const int cy = min((int)(pi.y * c.cinv[1]), c.nc[1] - 1);
   const int cz = min((int)(pi.z * c.cinv[2]), c.nc[2] - 1);
-  const float rc2 = c.rc * c.rc, inv_rc = 1.0f / c.rc;
+  const float rc2 = c.rc * c.rc;
+  int cnt = 0;
   for (int dz = -1; dz <= 1; ++dz) {
     const int zz = (cz + dz + c.nc[2]) % c.nc[2];
     for (int dy = -1; dy <= 1; ++dy) {
@@ -152,51 +188,54 @@ __global__ void __launch_bounds__(128) k_descriptor(const float4* __restrict__ c
       for (int dx = -1; dx <= 1; ++dx) {
         const int xx = (cx + dx + c.nc[0]) % c.nc[0];
         const int cell = (zz * c.nc[1] + yy) * c.nc[0] + xx;
-        const int j1 = start[cell + 1];
-        for (int j = start[cell]; j < j1; ++j) {
-          if (j == i) continue;
-          const float4 pj = cpos[j];
-          float d0 = pj.x - pi.x, d1 = pj.y - pi.y, d2 = pj.z - pi.z;
-          d0 -= c.L[0] * rintf(d0 * c.invL[0]);
-          d1 -= c.L[1] * rintf(d1 * c.invL[1]);
-          d2 -= c.L[2] * rintf(d2 * c.invL[2]);
-          const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
-          if (r2 >= rc2 || r2 == 0.0f) continue;
-          const float r = sqrtf(r2), ir = 1.0f / r;
-          const float s = 0.5f * (1.0f + __cosf(3.14159265358979f * r * inv_rc));
-          const float xk = 2.0f * r * inv_rc - 1.0f;
-          const float w = pj.w * s;
-          const float u1 = d0 * ir, u2 = d1 * ir, u3 = d2 * ir;
-          float tm = 1.0f, t = xk;  // T_0, T_1
-#pragma unroll
-          for (int k = 0; k < 32; ++k) {
-            float g;
-            if (k == 0) g = 1.0f;
-            else if (k == 1) g = xk;
-            else { const float tn = 2.0f * xk * t - tm; tm = t; t = tn; g = tn; }
-            const float wg = w * g;
-            T[k][0] += wg;
-            T[k][1] += wg * u1;
-            T[k][2] += wg * u2;
-            T[k][3] += wg * u3;
+        const int j0 = start[cell], j1 = start[cell + 1];
+        for (int jb = j0; jb < j1; jb += kDescLanes) {
+          const int j = jb + g;
+          bool in = false;
+          if (j < j1 && j != i) {
+            const float4 pj = cpos[j];
+            float d0 = pj.x - pi.x, d1 = pj.y - pi.y, d2 = pj.z - pi.z;
+            d0 -= c.L[0] * rintf(d0 * c.invL[0]);
+            d1 -= c.L[1] * rintf(d1 * c.invL[1]);
+            d2 -= c.L[2] * rintf(d2 * c.invL[2]);
+            const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            in = r2 < rc2 && r2 > 0.0f;
+          }
+          const unsigned gm = (unsigned)(__ballot(in) >> gbase) & ((1u << kDescLanes) - 1u);
+          if (in) list[cnt + __popc(gm & ((1u << g) - 1u))] = j;
+          cnt += __popc(gm);
+          if (cnt > kNbrMax - kDescLanes) {  // the same decision on all four lanes
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            accumulate_pairs(T, pi, cpos, list, cnt, g, c);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            cnt = 0;
           }
         }
       }
     }
   }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  accumulate_pairs(T, pi, cpos, list, cnt, g, c);
   float* to = Tout + (size_t)i * 128;
 #pragma unroll
-  for (int k = 0; k < 32; ++k) {
-    reinterpret_cast<float4*>(to)[k] = make_float4(T[k][0], T[k][1], T[k][2], T[k][3]);
+  for (int m = 0; m < 8; ++m)
+    reinterpret_cast<float4*>(to)[g + 4 * m] = make_float4(T[m][0], T[m][1], T[m][2], T[m][3]);
+  // invariants D[4k + l] = sum_a T[k][a] T[l][a], l < 4: T[l] is order 0 of lane l
+  float Tl[4][4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) Tl[l][a] = __shfl(T[0][a], gbase + l, 64);
   }
   const float* mu = params + kOffMu;
   const float* isd = params + kOffIsd;
   unsigned short* xo = X + (size_t)i * 128;
 #pragma unroll
-  for (int k = 0; k < 32; ++k) {
+  for (int m = 0; m < 8; ++m) {
+    const int k = g + 4 * m;
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
-      const float d = T[k][0] * T[l][0] + T[k][1] * T[l][1] + T[k][2] * T[l][2] + T[k][3] * T[l][3];
+      const float d = T[m][0] * Tl[l][0] + T[m][1] * Tl[l][1] + T[m][2] * Tl[l][2] + T[m][3] * Tl[l][3];
       const int f = 4 * k + l;
       xo[f] = f2bf((d - mu[f]) * isd[f]);
     }
@@ -204,18 +243,52 @@ __global__ void __launch_bounds__(128) k_descriptor(const float4* __restrict__ c
 }
 
 // ---------------------------------------------------------------------------
-// MLP forward + force head.  Block = 4 waves = 128 particles, wave w owns
-// rows 32w..32w+31.  Weights (bf16, transposed: Wt[out][in]) and biases are
-// staged in LDS; activations go layer to layer through LDS.  In training
-// mode the pre-activations z1..z3 and activations h1..h3 are stored, and the
-// head also forms the loss and dL/dc.
+// LDS operand layout for the MFMA tiles: every matrix is stored with the
+// contraction index k contiguous and rows padded by 4 bf16 (8 bytes), so a
+// lane's four k values are one 64-bit LDS read and the 32 rows a half-wave
+// reads fall on distinct banks (row pitch / 8 bytes is odd).
+// ---------------------------------------------------------------------------
+constexpr int kPadIn = kIn + 4;     // 132: rows of 128 bf16
+constexpr int kPadH = kH + 4;       // 68: rows of 64 bf16
+constexpr int kPadO = kOut + 4;     // 36: rows of 32 bf16
+constexpr int kPadRows = kRows + 4; // 132: transposed tiles (rows = features, k = particles)
+
+// acc (32 x 32) += A (32 x K) * B (K x 32) with both operands k-contiguous:
+// A(m, k) = A[m * lda + k], B(k, n) = B[n * ldb + k]; lane l supplies
+// A(l % 32, 4 (l / 32) + i) and B(4 (l / 32) + i, l % 32), i < 4.
+__device__ __forceinline__ void mfma_tile_kc(f32x16& acc, const unsigned short* A, int lda,
+                                             const unsigned short* B, int ldb, int K) {
+  const int l = threadIdx.x & 63;
+  const int mn = l & 31, kh = (l >> 5) * 4;
+  const unsigned short* pa = A + mn * lda + kh;
+  const unsigned short* pb = B + mn * ldb + kh;
+#pragma unroll 4
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    const bf16x4 a = *reinterpret_cast<const bf16x4*>(pa + k0);
+    const bf16x4 b = *reinterpret_cast<const bf16x4*>(pb + k0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+  }
+}
+
+// weight offsets in the padded LDS copies
+constexpr int kLW1t = 0, kLW2t = kLW1t + kH * kPadIn, kLW3t = kLW2t + kH * kPadH,
+              kLW4t = kLW3t + kH * kPadH, kLWt = kLW4t + kOut * kPadH;  // [out][in] copies
+constexpr int kLW1 = 0, kLW2 = kLW1 + kIn * kPadH, kLW3 = kLW2 + kH * kPadH, kLW4 = kLW3 + kH * kPadH,
+              kLW = kLW4 + kH * kPadO;                                   // [in][out] copies
+
+// ---------------------------------------------------------------------------
+// MLP forward + force head.  Persistent blocks of 4 waves stage the weights
+// (bf16, [out][in]) and biases once, then walk tiles of 128 particles; wave w
+// owns rows 32w..32w+31 of a tile.  Activations go layer to layer through
+// LDS.  In training mode the pre-activations z1..z3 and activations h1..h3
+// are stored, and the head also forms the loss and dL/dc.
 // ---------------------------------------------------------------------------
 struct FwdLds {
-  unsigned short wt[kNWeights];   // W1t [64][128], W2t [64][64], W3t [64][64], W4t [32][64]
+  unsigned short wt[kLWt];
   float b[kH * 3 + kOut];
-  unsigned short x[kRows][kIn];
-  unsigned short h[2][kRows][kH];
-  float c[kRows][kOut];
+  unsigned short x[kRows][kPadIn];
+  unsigned short h[2][kRows][kPadH];
+  float c[kRows][kOut + 1];
   double lred[4];
 };
 
@@ -232,100 +305,116 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restric
                                                  float* __restrict__ dC, double* __restrict__ loss_part, float gscale) {
   extern __shared__ __align__(16) unsigned char smem[];
   FwdLds& S = *reinterpret_cast<FwdLds*>(smem);
-  const int row0 = blockIdx.x * kRows;
   const int tid = threadIdx.x, wave = tid >> 6;
-  for (int e = tid; e < kNWeights; e += blockDim.x) S.wt[e] = wt_g[e];
+  // weights: global [out][in] (dense) -> LDS rows padded
+  {
+    const int rows[4] = {kH, kH, kH, kOut}, cols[4] = {kIn, kH, kH, kH};
+    const int gofs[4] = {0, kIn * kH, kIn * kH + kH * kH, kIn * kH + 2 * kH * kH};
+    const int lofs[4] = {kLW1t, kLW2t, kLW3t, kLW4t}, pitch[4] = {kPadIn, kPadH, kPadH, kPadH};
+#pragma unroll
+    for (int L = 0; L < 4; ++L)
+      for (int e = tid; e < rows[L] * cols[L]; e += blockDim.x) {
+        const int r = e / cols[L], c = e - r * cols[L];
+        S.wt[lofs[L] + r * pitch[L] + c] = wt_g[gofs[L] + e];
+      }
+  }
   for (int e = tid; e < kH; e += blockDim.x) {
     S.b[e] = params[kOffB1 + e];
     S.b[kH + e] = params[kOffB2 + e];
     S.b[2 * kH + e] = params[kOffB3 + e];
   }
   for (int e = tid; e < kOut; e += blockDim.x) S.b[3 * kH + e] = params[kOffB4 + e];
-  for (int e = tid; e < kRows * kIn / 4; e += blockDim.x) {
-    const int r = e / (kIn / 4), c4 = e % (kIn / 4);
-    uint2 v = make_uint2(0u, 0u);
-    if (row0 + r < n) v = reinterpret_cast<const uint2*>(X + (size_t)(row0 + r) * kIn)[c4];
-    reinterpret_cast<uint2*>(&S.x[r][0])[c4] = v;
-  }
-  __syncthreads();
 
-  const int wr = wave * 32;  // this wave's first row in the block
-  const unsigned short* wl[4] = {S.wt, S.wt + kIn * kH, S.wt + kIn * kH + kH * kH, S.wt + kIn * kH + 2 * kH * kH};
-  // hidden layers
-#pragma unroll
-  for (int layer = 0; layer < 3; ++layer) {
-    const int K = layer == 0 ? kIn : kH;
-    const unsigned short* A = layer == 0 ? &S.x[wr][0] : &S.h[(layer - 1) & 1][wr][0];
-    const int lda = layer == 0 ? kIn : kH;
-    unsigned short* Hout = &S.h[layer & 1][wr][0];
-#pragma unroll
-    for (int nt = 0; nt < kH / 32; ++nt) {
-      f32x16 acc;
-      zero(acc);
-      // B(k, n) = W[k][n] = Wt[n][k]
-      mfma_tile(acc, A, lda, 1, wl[layer] + nt * 32 * K, 1, K, K);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = acc_row(r), col = nt * 32 + acc_col();
-        const float z = acc[r] + S.b[layer * kH + col];
-        const float h = silu(z);
-        const unsigned short hb = f2bf(h);
-        Hout[row * kH + col] = hb;
-        if (TRAIN && row0 + wr + row < n) {
-          Z[((size_t)layer * n + row0 + wr + row) * kH + col] = z;
-          H[((size_t)layer * n + row0 + wr + row) * kH + col] = hb;
-        }
-      }
+  const int wr = wave * 32;  // this wave's first row in the tile
+  const unsigned short* wl[4] = {S.wt + kLW1t, S.wt + kLW2t, S.wt + kLW3t, S.wt + kLW4t};
+  const int ldw[4] = {kPadIn, kPadH, kPadH, kPadH};
+  double lsum = 0.0;
+  const int ntiles = (n + kRows - 1) / kRows;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int row0 = tile * kRows;
+    __syncthreads();  // previous tile done with S.x / S.c; weights staged
+    for (int e = tid; e < kRows * kIn / 4; e += blockDim.x) {
+      const int r = e / (kIn / 4), c4 = e % (kIn / 4);
+      uint2 v = make_uint2(0u, 0u);
+      if (row0 + r < n) v = reinterpret_cast<const uint2*>(X + (size_t)(row0 + r) * kIn)[c4];
+      *reinterpret_cast<uint2*>(&S.x[r][4 * c4]) = v;
     }
     __syncthreads();
-  }
-  // output layer: c = h3 W4 + b4
-  {
-    f32x16 acc;
-    zero(acc);
-    mfma_tile(acc, &S.h[0][wr][0], kH, 1, wl[3], 1, kH, kH);
+    // hidden layers
 #pragma unroll
-    for (int r = 0; r < 16; ++r) S.c[wr + acc_row(r)][acc_col()] = acc[r] + S.b[3 * kH + acc_col()];
-  }
-  __syncthreads();
-
-  // head: one thread per particle (threads 0..127)
-  double lsum = 0.0;
-  if (tid < kRows && row0 + tid < n) {
-    const int slot = row0 + tid;
-    const float* Tp = Tin + (size_t)slot * 128;
-    const float q = cpos[slot].w;
-    float f0 = 0.f, f1 = 0.f, f2 = 0.f;
-#pragma unroll 8
-    for (int k = 0; k < kOut; ++k) {
-      const float4 t = reinterpret_cast<const float4*>(Tp)[k];
-      const float cc = S.c[tid][k];
-      f0 += cc * t.y;
-      f1 += cc * t.z;
-      f2 += cc * t.w;
+    for (int layer = 0; layer < 3; ++layer) {
+      const int K = layer == 0 ? kIn : kH;
+      const unsigned short* A = layer == 0 ? &S.x[wr][0] : &S.h[(layer - 1) & 1][wr][0];
+      const int lda = layer == 0 ? kPadIn : kPadH;
+      unsigned short* Hout = &S.h[layer & 1][wr][0];
+#pragma unroll
+      for (int nt = 0; nt < kH / 32; ++nt) {
+        f32x16 acc;
+        zero(acc);
+        mfma_tile_kc(acc, A, lda, wl[layer] + nt * 32 * ldw[layer], ldw[layer], K);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = acc_row(r), col = nt * 32 + acc_col();
+          const float z = acc[r] + S.b[layer * kH + col];
+          const float h = silu(z);
+          const unsigned short hb = f2bf(h);
+          Hout[row * kPadH + col] = hb;
+          if (TRAIN && row0 + wr + row < n) {
+            Z[((size_t)layer * n + row0 + wr + row) * kH + col] = z;
+            H[((size_t)layer * n + row0 + wr + row) * kH + col] = hb;
+          }
+        }
+      }
+      __syncthreads();
     }
-    const float sq = s_out * q;
-    f0 *= sq; f1 *= sq; f2 *= sq;
-    const int src = cidx[slot];
-    float* out = (src < n_ion) ? ion_dF + 3 * (int64_t)src : wc_dF + 3 * ((int64_t)src - n_ion);
-    if (accumulate) { out[0] += f0; out[1] += f1; out[2] += f2; }
-    else { out[0] = f0; out[1] = f1; out[2] = f2; }
-    if (TRAIN) {
-      const float* tg = (src < n_ion) ? ion_tgt + 3 * (int64_t)src : wc_tgt + 3 * ((int64_t)src - n_ion);
-      const float e0 = f0 - tg[0], e1 = f1 - tg[1], e2 = f2 - tg[2];
-      lsum = (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
-      // dL/d dF = gscale * e (gscale = 2 / (3 n)); dL/dc_k = s_out q (g . T[k, 1:4])
-      const float g0 = gscale * e0 * sq, g1 = gscale * e1 * sq, g2 = gscale * e2 * sq;
+    // output layer: c = h3 W4 + b4
+    {
+      f32x16 acc;
+      zero(acc);
+      mfma_tile_kc(acc, &S.h[0][wr][0], kPadH, wl[3], ldw[3], kH);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) S.c[wr + acc_row(r)][acc_col()] = acc[r] + S.b[3 * kH + acc_col()];
+    }
+    __syncthreads();
+
+    // head: one thread per particle (threads 0..127)
+    if (tid < kRows && row0 + tid < n) {
+      const int slot = row0 + tid;
+      const float* Tp = Tin + (size_t)slot * 128;
+      const float q = cpos[slot].w;
+      float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 #pragma unroll 8
       for (int k = 0; k < kOut; ++k) {
         const float4 t = reinterpret_cast<const float4*>(Tp)[k];
-        dC[(size_t)slot * kOut + k] = g0 * t.y + g1 * t.z + g2 * t.w;
+        const float cc = S.c[tid][k];
+        f0 += cc * t.y;
+        f1 += cc * t.z;
+        f2 += cc * t.w;
+      }
+      const float sq = s_out * q;
+      f0 *= sq; f1 *= sq; f2 *= sq;
+      const int src = cidx[slot];
+      float* out = (src < n_ion) ? ion_dF + 3 * (int64_t)src : wc_dF + 3 * ((int64_t)src - n_ion);
+      if (accumulate) { out[0] += f0; out[1] += f1; out[2] += f2; }
+      else { out[0] = f0; out[1] = f1; out[2] = f2; }
+      if (TRAIN) {
+        const float* tg = (src < n_ion) ? ion_tgt + 3 * (int64_t)src : wc_tgt + 3 * ((int64_t)src - n_ion);
+        const float e0 = f0 - tg[0], e1 = f1 - tg[1], e2 = f2 - tg[2];
+        lsum += (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
+        // dL/d dF = gscale * e (gscale = 2 / (3 n)); dL/dc_k = s_out q (g . T[k, 1:4])
+        const float g0 = gscale * e0 * sq, g1 = gscale * e1 * sq, g2 = gscale * e2 * sq;
+#pragma unroll 8
+        for (int k = 0; k < kOut; ++k) {
+          const float4 t = reinterpret_cast<const float4*>(Tp)[k];
+          dC[(size_t)slot * kOut + k] = g0 * t.y + g1 * t.z + g2 * t.w;
+        }
       }
     }
   }
   if (TRAIN) {
     // deterministic block sum of the squared errors (threads 0..127 hold them)
     for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
+    __syncthreads();
     if ((tid & 63) == 0) S.lred[wave] = lsum;
     __syncthreads();
     if (tid == 0) loss_part[blockIdx.x] = S.lred[0] + S.lred[1] + S.lred[2] + S.lred[3];
@@ -335,13 +424,16 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restric
 // ---------------------------------------------------------------------------
 // MLP backward for one block of 128 particles: per-block partial gradients of
 // every weight and bias, written to gpart[block][kNTrain] (summed later in a
-// fixed order).  Weights are staged in LDS in their natural [in][out] layout.
+// fixed order).  Weights are staged in LDS in their natural [in][out] layout
+// (the k of dh = dz W^T is the output index); the layer input and dz are
+// also kept transposed (features x particles) for dW = act^T dz, whose k is
+// the particle index.  dz / dz^T are double-buffered across layers.
 // ---------------------------------------------------------------------------
 struct BwdLds {
-  unsigned short w[kNWeights];          // W1 [128][64], W2 [64][64], W3 [64][64], W4 [64][32]
-  unsigned short act[kRows][kIn];       // layer input (x or h), bf16
-  unsigned short dz[kRows][kH];         // gradient at the layer output (bf16)
-  unsigned short dzn[kRows][kH];        // gradient passed down (bf16)
+  unsigned short w[kLW];                  // W1 [128][68], W2 [64][68], W3 [64][68], W4 [64][36]
+  unsigned short actT[kIn][kPadRows];     // layer input, transposed
+  unsigned short dz[2][kRows][kPadH];     // gradient at the layer output (bf16)
+  unsigned short dzT[2][kH][kPadRows];    // the same, transposed
 };
 
 __global__ void __launch_bounds__(256) k_mlp_bwd(const unsigned short* __restrict__ X, const float* __restrict__ Z,
@@ -353,25 +445,39 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(const unsigned short* __restric
   const int row0 = blockIdx.x * kRows;
   const int tid = threadIdx.x, wave = tid >> 6;
   float* gp = gpart + (size_t)blockIdx.x * kNTrain;
-  for (int e = tid; e < kNWeights; e += blockDim.x) S.w[e] = w_g[e];
-  // dz <- dC (bf16, zero for rows past n)
+  {
+    const int rows[4] = {kIn, kH, kH, kH}, cols[4] = {kH, kH, kH, kOut};
+    const int gofs[4] = {0, kIn * kH, kIn * kH + kH * kH, kIn * kH + 2 * kH * kH};
+    const int lofs[4] = {kLW1, kLW2, kLW3, kLW4}, pitch[4] = {kPadH, kPadH, kPadH, kPadO};
+#pragma unroll
+    for (int L = 0; L < 4; ++L)
+      for (int e = tid; e < rows[L] * cols[L]; e += blockDim.x) {
+        const int r = e / cols[L], c = e - r * cols[L];
+        S.w[lofs[L] + r * pitch[L] + c] = w_g[gofs[L] + e];
+      }
+  }
+  // dz <- dC (bf16, zero for rows past n), both layouts
   for (int e = tid; e < kRows * kOut; e += blockDim.x) {
     const int r = e / kOut, k = e % kOut;
-    S.dz[r][k] = (row0 + r < n) ? f2bf(dC[(size_t)(row0 + r) * kOut + k]) : (unsigned short)0;
+    const unsigned short v = (row0 + r < n) ? f2bf(dC[(size_t)(row0 + r) * kOut + k]) : (unsigned short)0;
+    S.dz[0][r][k] = v;
+    S.dzT[0][k][r] = v;
   }
-  const int offW[4] = {0, kIn * kH, kIn * kH + kH * kH, kIn * kH + 2 * kH * kH};
+  const int offW[4] = {kLW1, kLW2, kLW3, kLW4};
+  const int pitW[4] = {kPadH, kPadH, kPadH, kPadO};
   const int offGW[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
   const int offGB[4] = {kOffB1, kOffB2, kOffB3, kOffB4};
   const int nin[4] = {kIn, kH, kH, kH};
   const int nout[4] = {kH, kH, kH, kOut};
+  int cur = 0;
   for (int layer = 3; layer >= 0; --layer) {
     const int ni = nin[layer], no = nout[layer];
-    // layer input activation (x for layer 0, h_layer otherwise)
+    // layer input activation (x for layer 0, h_layer otherwise), transposed
     for (int e = tid; e < kRows * ni; e += blockDim.x) {
-      const int r = e / ni, k = e % ni;
+      const int k = e / kRows, r = e - k * kRows;
       unsigned short v = 0;
       if (row0 + r < n) v = layer == 0 ? X[(size_t)(row0 + r) * kIn + k] : H[((size_t)(layer - 1) * n + row0 + r) * kH + k];
-      S.act[r][k] = v;
+      S.actT[k][r] = v;
     }
     __syncthreads();
     // weight gradient tiles: dW (ni x no) = act^T (ni x rows) * dz (rows x no)
@@ -380,44 +486,46 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(const unsigned short* __restric
       const int mi = t / tn, nj = t % tn;
       f32x16 acc;
       zero(acc);
-      // A(m, k) = act[k][m0 + m], B(k, n) = dz[k][n0 + n]
-      mfma_tile(acc, &S.act[0][mi * 32], 1, kIn, &S.dz[0][nj * 32], kH, 1, kRows);
+      mfma_tile_kc(acc, &S.actT[mi * 32][0], kPadRows, &S.dzT[cur][nj * 32][0], kPadRows, kRows);
 #pragma unroll
       for (int r = 0; r < 16; ++r)
         gp[offGW[layer] + (mi * 32 + acc_row(r)) * no + nj * 32 + acc_col()] = acc[r];
     }
-    // bias gradient: column sums of dz (fixed order)
+    // bias gradient: sums of dz over particles (fixed order)
     for (int col = tid; col < no; col += blockDim.x) {
       float s = 0.0f;
-      for (int r = 0; r < kRows; ++r) s += bf2f(S.dz[r][col]);
+      for (int r = 0; r < kRows; ++r) s += bf2f(S.dzT[cur][col][r]);
       gp[offGB[layer] + col] = s;
     }
     if (layer == 0) break;
     // gradient to the layer below: dh (rows x ni) = dz (rows x no) * W^T, then * silu'(z)
+    const int nxt = cur ^ 1;
     for (int t = wave; t < (kRows / 32) * (ni / 32); t += 4) {
       const int ri = t / (ni / 32), mj = t % (ni / 32);
       f32x16 acc;
       zero(acc);
       // A(m, k) = dz[r0 + m][k], B(k, n) = W[m0 + n][k]  (W stored [in][out])
-      mfma_tile(acc, &S.dz[ri * 32][0], kH, 1, S.w + offW[layer] + mj * 32 * no, 1, no, no);
+      mfma_tile_kc(acc, &S.dz[cur][ri * 32][0], kPadH, S.w + offW[layer] + mj * 32 * pitW[layer], pitW[layer], no);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = ri * 32 + acc_row(r), col = mj * 32 + acc_col();
         float v = 0.0f;
         if (row0 + row < n) v = acc[r] * dsilu(Z[((size_t)(layer - 1) * n + row0 + row) * kH + col]);
-        S.dzn[row][col] = f2bf(v);
+        const unsigned short b = f2bf(v);
+        S.dz[nxt][row][col] = b;
+        S.dzT[nxt][col][row] = b;
       }
     }
     __syncthreads();
-    for (int e = tid; e < kRows * kH; e += blockDim.x) (&S.dz[0][0])[e] = (&S.dzn[0][0])[e];
-    __syncthreads();
+    cur = nxt;
   }
 }
 
 // Sum of the per-block gradient partials in block order (deterministic) and
 // of the loss partials; gscale_loss converts the squared-error sum to the mean.
 __global__ void k_grad_reduce(const float* __restrict__ gpart, int nblk, float* __restrict__ grad,
-                              const double* __restrict__ loss_part, double loss_scale, double* __restrict__ loss) {
+                              const double* __restrict__ loss_part, int nloss, double loss_scale,
+                              double* __restrict__ loss) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < kNTrain) {
     float s = 0.0f;
@@ -426,7 +534,7 @@ __global__ void k_grad_reduce(const float* __restrict__ gpart, int nblk, float* 
   }
   if (p == 0 && loss) {
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += loss_part[b];
+    for (int b = 0; b < nloss; ++b) s += loss_part[b];
     *loss = s * loss_scale;
   }
 }

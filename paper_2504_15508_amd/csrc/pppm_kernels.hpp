@@ -4,12 +4,13 @@
 //   sorted   [n] T4 (d_x, d_y, d_z, q): fractional B-spline offsets and charge,
 //            ordered by bin; sidx [n] int: stencil starts s_x | s_y<<10 | s_z<<20;
 //            perm [n] int: original index (ions 0..n_ion-1, then WCs).
-//   bins     one per (x split s_x / xs, stencil-start plane s_z, stencil-start
-//            row group s_y >> qshift), in that order of significance;
-//            bin_start [nbins+1].
+//   bins     one per (split, stencil-start plane s_z, stencil-start row group
+//            s_y >> qshift), in that order of significance; bin_start
+//            [nbins+1].  The split is s_x / xs for pencil tiles and the
+//            original index mod nsplit for planes.
 //   spec     half spectrum [Kx/2+1][Kz][Ky] complex (y fastest); the spread
-//            writes one such partial spectrum per x split, the forward y pass
-//            sums them in split order into the first.
+//            writes one such partial spectrum per particle split; the pass
+//            after it adds them in split order.
 //   fspec    three field spectra [3][Kx/2+1][Kz][Ky] complex.
 //   G        FP64 influence table [Kx/2+1][Ky/2+1][Kz/2+1] (G is even in
 //            every wave-vector component).
@@ -30,8 +31,9 @@ struct Geo {
   int Kh;        // Kx/2 + 1
   int qshift;    // rows per bin group = 2^qshift (4 for pencil tiles, 16 for planes)
   int NQ;        // Ky >> qshift
-  int nsplit;    // x splits of the spread (particles binned by s_x / xs)
-  int xs;        // Kx / nsplit
+  int nsplit;    // particle splits of the spread (one partial spectrum each)
+  int xs;        // Kx / nsplit: split = s_x / xs (pencil tiles) ...
+  int split_by_index;  // ... or split = original index mod nsplit (planes)
   int nbins;     // nsplit * Kz * NQ
   int scy, scz;  // spread pencil cross-section (y, z); the pencil spans all x
   int spy, spz;  // spread pencil counts
@@ -104,7 +106,8 @@ __device__ __forceinline__ void particle_bin(const T* __restrict__ ion_pos, cons
     s[a] = sa;
   }
   spack = s[0] | (s[1] << 10) | (s[2] << 20);
-  bin = ((s[0] / g.xs) * g.K[2] + s[2]) * g.NQ + (s[1] >> g.qshift);
+  const int split = g.split_by_index ? (int)(i & (g.nsplit - 1)) : s[0] / g.xs;
+  bin = (split * g.K[2] + s[2]) * g.NQ + (s[1] >> g.qshift);
 }
 
 // |q| as an unsigned integer whose order is that of the float (non-negative
@@ -572,14 +575,14 @@ __global__ void __launch_bounds__(512) k_spread_fftx(const T4<T>* __restrict__ s
 // ----------------------------------------------------------------------------
 // Plane spread with both forward in-plane transforms (used when one z plane
 // fits in LDS).  Block (z, split) owns mesh plane z and visits every particle
-// whose stencil-start plane is one of z-p+1 .. z (and whose stencil-start
-// column is in its x split); each visit adds the particle's p x p points of
+// whose stencil-start plane is one of z-p+1 .. z (and whose original index
+// falls in its split); each visit adds the particle's p x p points of
 // that plane with the single z weight of the plane.  With no halo in x or y
 // every visit does the same work, and no per-row ownership tests are needed.
 // The plane is then converted to complex row pairs, transformed along x
 // (real-to-complex, two rows per complex FFT), rearranged to [kx][y] and
 // transformed along y, and written as spec[kx][z][y] (one partial spectrum
-// per x split; the z pass adds them in split order).
+// per split; the z pass adds them in split order).
 // ----------------------------------------------------------------------------
 template <typename T, int P>
 __global__ void __launch_bounds__(1024) k_spread_xy(const T4<T>* __restrict__ sorted,
@@ -734,7 +737,7 @@ __global__ void __launch_bounds__(1024) k_spread_xy(const T4<T>* __restrict__ so
   }
 }
 
-// Sum of the partial spectra of the x splits in split order (inspection copy).
+// Sum of the partial spectra of the particle splits in split order (inspection copy).
 template <typename T>
 __global__ void k_sum_partials(cpx<T>* __restrict__ dst, const cpx<T>* __restrict__ src, int nsum, size_t stride,
                                size_t n) {
@@ -747,7 +750,7 @@ __global__ void k_sum_partials(cpx<T>* __restrict__ dst, const cpx<T>* __restric
 
 // ----------------------------------------------------------------------------
 // Transforms along y of contiguous blocks of zb rows (forward on the charge
-// spectrum, after adding the partial spectra of the x splits; inverse on the
+// spectrum, after adding the partial spectra of the particle splits; inverse on the
 // three field spectra).
 // Used forward on spec and inverse on the three field spectra.
 // ----------------------------------------------------------------------------
@@ -797,7 +800,7 @@ __global__ void __launch_bounds__(256) k_ffty(cpx<T>* __restrict__ data, const c
       const int e = b0 + u * blockDim.x;
       if (e < n) r[u] = base[e];
     }
-    // partial spectra of the other x splits, added in split order
+    // partial spectra of the other particle splits, added in split order
     for (int sp = 1; sp < nsum; ++sp) {
       const cpx<T>* ps = base + (size_t)sp * sum_stride;
 #pragma unroll
@@ -857,7 +860,7 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
       const int e = base + u * blockDim.x;
       if (e < n) r[u] = spec[col0 + imul(e >> lyb, Ky) + (e & (yb - 1))];
     }
-    // partial spectra of the other x splits, added in split order
+    // partial spectra of the other particle splits, added in split order
     for (int sp = 1; sp < nsum; ++sp) {
       const cpx<T>* ps = spec + (size_t)sp * sum_stride;
 #pragma unroll
