@@ -47,6 +47,11 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned coarse-mesh leg")
     ap.add_argument("--learned-boxes", type=int, default=2000, help="training boxes for the learned leg")
     ap.add_argument("--learned-epochs", type=int, default=3)
+    ap.add_argument("--copy-ref-mb", type=float, default=0.0,
+                    help="also run a plain device copy of this size (reference for rocprofv3 byte counters)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--copy-ref-mb run into profiles/hbm_traffic.json, then exit")
     return ap.parse_args()
 
 
@@ -80,6 +85,60 @@ def kernel_bytes(stage: str, N: int, K: int, order: int) -> float:
         # fields read once + particles (d, q, stencil start, perm) + forces
         return 3 * 4 * K ** 3 + part + N * 4 + N * 12
     return 0.0
+
+
+# kernel-name prefix -> stage name of the library instrumentation
+KERNEL_STAGES = [("k_spread_xy", "spread_xy"), ("k_spread_fftx", "spread_fftx"), ("k_ffty<float, false>", "ffty_fwd"),
+                 ("k_fftz_poisson", "fftz_poisson"), ("k_ffty<float, true>", "ffty_inv_reduce"),
+                 ("k_ifftx", "ifftx"), ("k_gather", "gather"), ("k_bin_hist", "bin_count"),
+                 ("k_bin_place", "bin_scatter"), ("k_bin_colscan", "bin_scan"), ("k_bin_totscan", "bin_scan")]
+
+
+def ingest_counters(fetch_csv: str, write_csv: str, copy_mb: float) -> dict:
+    """Per-launch HBM-side bytes of every kernel of the benchmark step from two
+    rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each
+    scaled by what the same counter reads for a plain copy of copy_mb MB."""
+    import csv
+    import statistics
+
+    def load(path, counter):
+        per, copies = {}, []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name, val = r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0
+            per.setdefault(name, []).append(val)
+            if "copy" in name.lower():
+                copies.append((name, val))
+        return per, copies
+
+    copy_bytes = copy_mb * 1e6
+
+    def scale(copies):
+        # the reference copy's dispatches: the copy-kernel dispatches within 2x of its size
+        near = [v for _, v in copies if 0.5 * copy_bytes <= v <= 2.0 * copy_bytes]
+        if not near:
+            raise RuntimeError("no copy dispatch of the reference size in the counter run (use --copy-ref-mb)")
+        return statistics.median(near) / copy_bytes, next(n for n, v in copies if v in near)
+
+    (fetch, fc), (write, wc) = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    f_scale, ck = scale(fc)
+    w_scale, _ = scale(wc)
+    out = {"source_digest": source_digest(), "copy_kernel": ck.split("(")[0], "copy_mb": copy_mb,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    for name, vals in fetch.items():
+        stage = next((st for pre, st in KERNEL_STAGES if pre in name), None)
+        if stage is None:
+            continue
+        wv = write.get(name, [0.0])
+        fb = statistics.median(vals) / f_scale
+        wb = statistics.median(wv) / w_scale
+        rec = out["kernels"].setdefault(stage, {"fetch_bytes": 0.0, "write_bytes": 0.0, "bytes_per_launch": 0.0})
+        # several kernels can share a stage (the scans): add them
+        rec["fetch_bytes"] += fb
+        rec["write_bytes"] += wb
+        rec["bytes_per_launch"] = rec["fetch_bytes"] + rec["write_bytes"]
+    return out
 
 
 def source_digest() -> str:
@@ -204,6 +263,13 @@ def learned_leg(args, w, s0, ion_d, wc_d, qi, qw, dev, timed_graph_fn, plain_ms,
 
 def main():
     args = parse()
+    if args.ingest_counters:
+        out = ingest_counters(args.ingest_counters[0], args.ingest_counters[1], args.copy_ref_mb or 256.0)
+        path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+        with open(path, "w") as fh:
+            json.dump(out, fh, indent=1)
+        print(json.dumps(out))
+        return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1.",
@@ -291,6 +357,14 @@ def main():
         return dt, prof
 
     result = {}
+    if args.copy_ref_mb > 0:
+        nb = int(args.copy_ref_mb * 1e6 / 4)
+        xs = torch.ones(nb, dtype=torch.float32, device=dev)
+        ys = torch.empty_like(xs)
+        for _ in range(3):
+            ys.copy_(xs)
+        torch.cuda.synchronize()
+        del xs, ys
     if args.eager_only:
         sec = None
     else:
