@@ -140,31 +140,56 @@ __global__ void __launch_bounds__(256) k_bin_count(const T* __restrict__ ion_pos
 __global__ void __launch_bounds__(1024) k_bin_scan(int* __restrict__ count, int* __restrict__ start,
                                                    int* __restrict__ cursor, int nbins,
                                                    unsigned* __restrict__ qmax_bits = nullptr) {
-  if (qmax_bits && threadIdx.x == 0) *qmax_bits = 0u;
+  // tiles of 4 bins per thread, loaded and stored coalesced; the running
+  // offset is carried from tile to tile
   __shared__ int part[1024];
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int chunk = (nbins + nt - 1) / nt;
-  const int b0 = min(nbins, t * chunk), b1 = min(nbins, b0 + chunk);
-  int s = 0;
-  for (int b = b0; b < b1; ++b) s += count[b];
-  part[t] = s;
+  __shared__ int vals[4096];
+  __shared__ int carry;
+  if (qmax_bits && threadIdx.x == 0) *qmax_bits = 0u;
+  const int t = threadIdx.x, nt = blockDim.x, tile = 4 * nt;
+  if (t == 0) carry = 0;
+  for (int b0 = 0; b0 < nbins; b0 += tile) {
+    int c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * nt + t;  // coalesced
+      c[u] = b < nbins ? count[b] : 0;
+    }
+    __syncthreads();  // carry of the previous tile is final; vals is free
+    // this thread's 4 bins are b0 + 4t .. b0 + 4t + 3: exchange through LDS
+#pragma unroll
+    for (int u = 0; u < 4; ++u) vals[u * nt + t] = c[u];
+    __syncthreads();
+    int v4[4], s = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { v4[u] = vals[4 * t + u]; s += v4[u]; }
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+      const int x = (t >= off) ? part[t - off] : 0;
+      __syncthreads();
+      part[t] += x;
+      __syncthreads();
+    }
+    int run = carry + part[t] - s;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { vals[4 * t + u] = run; run += v4[u]; }
+    __syncthreads();
+    const int tot = part[nt - 1];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * nt + t;
+      if (b < nbins) {
+        start[b] = vals[u * nt + t];
+        cursor[b] = vals[u * nt + t];
+        count[b] = 0;
+      }
+    }
+    __syncthreads();
+    if (t == 0) carry += tot;
+  }
   __syncthreads();
-  // Hillis-Steele inclusive scan of the per-thread sums
-  for (int off = 1; off < nt; off <<= 1) {
-    int v = (t >= off) ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int run = part[t] - s;
-  for (int b = b0; b < b1; ++b) {
-    const int c = count[b];
-    start[b] = run;
-    cursor[b] = run;
-    count[b] = 0;
-    run += c;
-  }
-  if (t == nt - 1) start[nbins] = part[t];
+  if (t == 0) start[nbins] = carry;
 }
 
 template <typename T, int P>

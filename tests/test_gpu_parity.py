@@ -169,6 +169,12 @@ def test_pencil_tile_path_matches_pppm_oracle(torch_dev, precision):
     check_vs_pppm(torch_dev, s, (256, 128, 16), 5, precision, tol, tole, tole)
 
 
+# Global-atomic counting sort (bins that do not fit in LDS: > 16384 bins)
+def test_fp64_global_sort_path_matches_pppm_oracle(torch_dev):
+    s = systems.workload(1).system()
+    check_vs_pppm(torch_dev, s, (256, 256, 512), 5, "fp64", 1e-10, 1e-10, 1e-10)
+
+
 # ---------------------------------------------------------------------------
 # The 216,576-atom system (72,192 waters + 72,192 WCs, 129.3 A, 128^3) in the
 # plan configuration the benchmark times: every force against the FP64 PPPM
