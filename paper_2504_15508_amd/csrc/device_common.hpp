@@ -72,6 +72,168 @@ __device__ __forceinline__ void dft_small(cpx<T>* v) {
   }
 }
 
+// LDS row padding: one spare element after every 16 (see the Stockham passes below).
+__device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
+__host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4); }
+
+// 16-point DFT in registers as 4 x 4 (n = a + 4b, k = c + 4d):
+// X[c + 4d] = sum_a W4^{ad} W16^{ac} sum_b x[a + 4b] W4^{bc}.  In place,
+// natural order in and out.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(cpx<T>* x) {
+  const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173, r2 = (T)0.70710678118654752440;
+  cpx<T> t[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    cpx<T> b0 = x[a], b1 = x[a + 4], b2 = x[a + 8], b3 = x[a + 12];
+    dft4<T, INV>(b0, b1, b2, b3);
+    t[a][0] = b0; t[a][1] = b1; t[a][2] = b2; t[a][3] = b3;
+  }
+  // twiddles W16^{ac} (a, c = 1..3); W16 = exp(-+ 2 pi i / 16)
+  const T sg = INV ? (T)1 : (T)-1;
+  const cpx<T> w1{c1, sg * s1}, w2{r2, sg * r2}, w3{s1, sg * c1};
+  const cpx<T> w4{(T)0, sg}, w6{-r2, sg * r2}, w9{-c1, -sg * s1};
+  t[1][1] = cmul(t[1][1], w1); t[1][2] = cmul(t[1][2], w2); t[1][3] = cmul(t[1][3], w3);
+  t[2][1] = cmul(t[2][1], w2); t[2][2] = cmul(t[2][2], w4); t[2][3] = cmul(t[2][3], w6);
+  t[3][1] = cmul(t[3][1], w3); t[3][2] = cmul(t[3][2], w6); t[3][3] = cmul(t[3][3], w9);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    cpx<T> d0 = t[0][c], d1 = t[1][c], d2 = t[2][c], d3 = t[3][c];
+    dft4<T, INV>(d0, d1, d2, d3);
+    x[c] = d0; x[c + 4] = d1; x[c + 8] = d2; x[c + 12] = d3;
+  }
+}
+
+// L-point DFT in registers, L in {1, 2, 4, 8, 16}, natural order.
+template <typename T, int L, bool INV>
+__device__ __forceinline__ void dft_l(cpx<T>* v) {
+  if constexpr (L == 2) {
+    const cpx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (L == 4) {
+    dft4<T, INV>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (L == 8) {
+    dft8<T, INV>(v);
+  } else if constexpr (L == 16) {
+    dft16<T, INV>(v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched in-place FFTs of length N = 16 L (L in {1, 2, 4, 8, 16}) on rows held
+// in LDS, computed in registers: L threads per row, 16 values per thread, one
+// exchange through the row itself.  With n = l + L n1 and k = k1 + 16 k2,
+//   X[k1 + 16 k2] = sum_l W_L^{l k2} W_N^{l k1} sum_n1 x[l + L n1] W_16^{n1 k1}:
+// thread l transforms x[l + L n1] over n1 (16 points), multiplies by
+// W_N^{l k1} and writes to slot k1 L + l; thread m then reads slots
+// 16 m .. 16 m + 15 (k1 = m J + j, J = 16 / L, all l) and transforms over l
+// (L points), writing X in natural order.  The inverse runs the steps
+// backwards with conjugate twiddles.  Element e of row r lives at
+// buf[r * rstride + (PAD ? lds_pad(e) : e * estride)]; rows_fast selects
+// whether consecutive threads walk rows (column layouts) or the L threads of
+// one row.  Every thread of the block must call it (it synchronises).
+// ---------------------------------------------------------------------------
+template <typename T, int L, bool INV, bool PAD>
+__device__ __forceinline__ void fft_rows_reg(cpx<T>* buf, int nrows, int rstride, int estride, bool rows_fast,
+                                             const cpx<T>* tw, int twN) {
+  constexpr int N = 16 * L, J = 16 / L;
+  const int t = threadIdx.x;
+  const bool act = t < nrows * L;
+  int r = 0, l = 0;
+  if (act) {
+    if (rows_fast) { l = t / nrows; r = t - l * nrows; }
+    else { r = t / L; l = t - r * L; }
+  }
+  cpx<T>* row = buf + r * rstride;
+  auto at = [&](int e) -> cpx<T>& { return row[PAD ? lds_pad(e) : e * estride]; };
+  const int step = twN / N;
+  cpx<T> v[16];
+  if constexpr (!INV) {
+    if (act) {
+#pragma unroll
+      for (int n1 = 0; n1 < 16; ++n1) v[n1] = at(l + L * n1);
+    }
+    __syncthreads();
+    if (act) {
+      dft16<T, false>(v);
+#pragma unroll
+      for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[((l * k1) & (N - 1)) * step]);
+#pragma unroll
+      for (int k1 = 0; k1 < 16; ++k1) at(k1 * L + l) = v[k1];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = at(16 * l + e);  // (k1 = l J + e / L, l' = e % L)
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        dft_l<T, L, false>(v + j * L);
+#pragma unroll
+        for (int k2 = 0; k2 < L; ++k2) at(l * J + j + 16 * k2) = v[j * L + k2];
+      }
+    }
+    __syncthreads();
+  } else {
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+#pragma unroll
+        for (int k2 = 0; k2 < L; ++k2) v[j * L + k2] = at(l * J + j + 16 * k2);
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        dft_l<T, L, true>(v + j * L);
+        const int k1 = l * J + j;
+#pragma unroll
+        for (int m = 1; m < L; ++m) {
+          cpx<T> w = tw[((m * k1) & (N - 1)) * step];
+          w.y = -w.y;
+          v[j * L + m] = cmul(v[j * L + m], w);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) at(16 * l + e) = v[e];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int k1 = 0; k1 < 16; ++k1) v[k1] = at(k1 * L + l);
+    }
+    __syncthreads();
+    if (act) {
+      dft16<T, true>(v);
+#pragma unroll
+      for (int n1 = 0; n1 < 16; ++n1) at(l + L * n1) = v[n1];
+    }
+    __syncthreads();
+  }
+}
+
+// Register FFTs for N = 16 L with L <= 16 when the block has enough threads
+// (FP32 only: the FP64 registers would spill); false when not applicable.
+template <typename T, bool INV, bool PAD>
+__device__ __forceinline__ bool fft_rows_try_reg(cpx<T>* buf, int nrows, int N, int rstride, int estride,
+                                                 bool rows_fast, const cpx<T>* tw, int twN) {
+  if constexpr (sizeof(T) != 4) return false;
+  const int L = N / 16;
+  if (N < 16 || N > 256 || nrows * L > (int)blockDim.x) return false;
+  switch (L) {
+    case 1: fft_rows_reg<T, 1, INV, PAD>(buf, nrows, rstride, estride, rows_fast, tw, twN); return true;
+    case 2: fft_rows_reg<T, 2, INV, PAD>(buf, nrows, rstride, estride, rows_fast, tw, twN); return true;
+    case 4: fft_rows_reg<T, 4, INV, PAD>(buf, nrows, rstride, estride, rows_fast, tw, twN); return true;
+    case 8: fft_rows_reg<T, 8, INV, PAD>(buf, nrows, rstride, estride, rows_fast, tw, twN); return true;
+    case 16: fft_rows_reg<T, 16, INV, PAD>(buf, nrows, rstride, estride, rows_fast, tw, twN); return true;
+  }
+  return false;
+}
+
 // ---------------------------------------------------------------------------
 // Batched 1D FFTs of length N on data held in LDS, in place.
 //
@@ -94,8 +256,6 @@ __device__ __forceinline__ void dft_small(cpx<T>* v) {
 // element e of a row lives at e + e / 16 (lds_pad).  Column transforms
 // (estride > 1) are laid out unpadded: their lanes already walk consecutive
 // words.
-__device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
-__host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4); }
 
 // 24-bit integer products (full rate on CDNA; 32-bit products issue at a
 // quarter of the rate).  Every LDS index and mesh index fits.
@@ -170,6 +330,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int nrows, float inv_nrow
 template <typename T, bool INV, int EPT, bool PAD = false>
 __device__ __forceinline__ void fft_rows(cpx<T>* buf, int nrows, int N, int rstride, int estride, bool rows_fast,
                                          const cpx<T>* tw, int twN) {
+  if (fft_rows_try_reg<T, INV, PAD>(buf, nrows, N, rstride, estride, rows_fast, tw, twN)) return;
   const float inv_nrows = 1.0f / (float)nrows;
   int lg = 31 - __clz(N);
   int Ns = 1;

@@ -32,6 +32,17 @@ thread_local std::string g_global_error;
 #ifndef DPLR_SPREAD_MAX_SPLIT
 #define DPLR_SPREAD_MAX_SPLIT 8
 #endif
+// launch shapes of the transform passes (complex elements per y-pass block,
+// y rows per inverse-x block, columns per z-pass block)
+#ifndef DPLR_FFTY_ELEMS
+#define DPLR_FFTY_ELEMS 2048
+#endif
+#ifndef DPLR_IFFTX_ROWS
+#define DPLR_IFFTX_ROWS 16
+#endif
+#ifndef DPLR_FFTZ_COLS
+#define DPLR_FFTZ_COLS 8
+#endif
 
 constexpr int kMinMesh = 16;
 constexpr int kMaxMesh = 512;
@@ -245,7 +256,7 @@ bool choose_geometry(dplr_lr_plan p) {
   }
 
   // inverse x pass: xyb rows of y of the three fields per block
-  g.xyb = std::min(16, Ky);
+  g.xyb = std::min(DPLR_IFFTX_ROWS, Ky);
   while (g.xyb > 2 && ((size_t)(3 * g.xyb / 2) * (padded_len(Kx) + 1) * cs + twb > budget ||
                        (long)(3 * g.xyb / 2) * Kx > (long)kEPT * 512))
     g.xyb /= 2;
@@ -254,18 +265,19 @@ bool choose_geometry(dplr_lr_plan p) {
   if (p->thr_ifftx > 512) return false;
 
   // y pass: blocks of zb contiguous rows, about 1024 complex elements
-  g.zb = std::max(1, std::min(Kz, 1024 / Ky));
+  g.zb = std::max(1, std::min(Kz, DPLR_FFTY_ELEMS / Ky));
   while (g.zb > 1 && (size_t)g.zb * (padded_len(Ky) + 1) * cs + twb > budget) g.zb /= 2;
   p->thr_ffty = round_threads((long)g.zb * Ky);
   // the inverse pass also hosts the final reduction: 7 doubles per thread
   p->lds_ffty = std::max((size_t)g.zb * (padded_len(Ky) + 1) * cs + twb, (size_t)7 * p->thr_ffty * sizeof(double));
 
   // z pass: yb columns x Kz x 3 fields
-  g.yb = std::min(16, Ky);
+  g.yb = std::min(DPLR_FFTZ_COLS, Ky);
   while (g.yb > 1 && ((size_t)3 * g.yb * Kz * cs + twb > budget || (long)3 * g.yb * Kz > (long)kEPT * 1024)) g.yb /= 2;
   p->lds_z = (size_t)3 * g.yb * Kz * cs + twb;
   p->thr_z = round_threads((long)3 * g.yb * Kz);
   g.nzblk = g.Kh * (Ky / g.yb);
+  g.zgroup = std::max<int>(1, (int)(128 / (g.yb * cs)));
   return true;
 }
 
@@ -408,7 +420,8 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
   pc.inv_4beta2 = 1.0 / (4.0 * p->cfg.beta * p->cfg.beta);
   {
     ProfScope ps(p, 5);
-    hipLaunchKernelGGL((k_fftz_poisson<T>), dim3(g.nzblk), dim3(p->thr_z), p->lds_z, s, spec,
+    hipLaunchKernelGGL((k_fftz_poisson<T>), dim3((g.nzblk + 8 * g.zgroup - 1) / (8 * g.zgroup) * 8 * g.zgroup),
+                       dim3(p->thr_z), p->lds_z, s, spec,
                        p->plane ? g.nsplit : 1, nspec, fspec, p->G, p->partials, tw, g, pc);
   }
   const double V = p->box[0] * p->box[1] * p->box[2];

@@ -42,6 +42,7 @@ struct Geo {
   int twN;       // twiddle table length (max K)
   int nzblk;     // z-pass blocks
   int xyb;       // y rows per block of the inverse x pass
+  int zgroup;    // z-pass column blocks per 128-byte output line (run on one XCD)
 };
 
 struct PoissonConsts {
@@ -597,6 +598,10 @@ __global__ void __launch_bounds__(512) k_spread_fftx(const T4<T>* __restrict__ s
   }
 }
 
+#ifndef DPLR_SPREAD_PB
+#define DPLR_SPREAD_PB 2
+#endif
+
 // ----------------------------------------------------------------------------
 // Plane spread with both forward in-plane transforms (used when one z plane
 // fits in LDS).  Block (z, split) owns mesh plane z and visits every particle
@@ -650,7 +655,7 @@ __global__ void __launch_bounds__(1024) k_spread_xy(const T4<T>* __restrict__ so
   }
 
   const int total = R.pre[R.n];
-  constexpr int PB = 2;  // particles fetched per thread before processing
+  constexpr int PB = DPLR_SPREAD_PB;  // particles fetched per thread before processing
   for (int v0 = threadIdx.x; v0 < total; v0 += PB * blockDim.x) {
     T4<T> pts[PB];
     int sps[PB];
@@ -875,7 +880,15 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
 
   const int lyb = 31 - __clz(yb);  // yb is a power of two
   const int nyb = Ky >> lyb;
-  const int kx = blockIdx.x / nyb, y0 = (blockIdx.x - kx * nyb) << lyb;
+  // XCD-aware order: the f consecutive column blocks that share 128-byte
+  // lines of the outputs run on one XCD (blocks are dealt to the 8 XCDs
+  // round-robin), so no line is written from two L2s.  The grid is padded to
+  // a multiple of 8 f; padding blocks leave at once.
+  const int f = g.zgroup;
+  const int bg = blockIdx.x / (8 * f), bw = blockIdx.x - bg * 8 * f;
+  const int blk = bg * 8 * f + (bw & 7) * f + (bw >> 3);
+  if (blk >= g.nzblk) return;
+  const int kx = blk / nyb, y0 = (blk - kx * nyb) << lyb;
   const unsigned col0 = (unsigned)imul(imul(kx, Kz), Ky) + y0;  // spec[kx][0][y0]
   const int n = Kz << lyb;                                      // elements (z, yl), yl fastest
   for (int base = threadIdx.x; base < n; base += 8 * blockDim.x) {
@@ -973,7 +986,7 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
     double v = 0;
     const int nw = (blockDim.x + 63) >> 6;
     for (int w = 0; w < nw; ++w) v += red[w][threadIdx.x];
-    partials[(size_t)blockIdx.x * 8 + threadIdx.x] = v;
+    partials[(size_t)blk * 8 + threadIdx.x] = v;
   }
 }
 
