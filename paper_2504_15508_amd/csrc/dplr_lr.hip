@@ -32,10 +32,20 @@ thread_local std::string g_global_error;
 #ifndef DPLR_SPREAD_MAX_SPLIT
 #define DPLR_SPREAD_MAX_SPLIT 8
 #endif
+// particle chunks of the counting sort (one LDS histogram each) and the
+// granularity of the chunk length; the per-bin chunk scan handles at most
+// 16 x 16 chunks
+#ifndef DPLR_SORT_CHUNKS
+#define DPLR_SORT_CHUNKS 256
+#endif
+static_assert(DPLR_SORT_CHUNKS >= 1 && DPLR_SORT_CHUNKS <= 256, "sort chunk count out of range");
+#ifndef DPLR_SORT_CHUNK_ALIGN
+#define DPLR_SORT_CHUNK_ALIGN 256
+#endif
 // launch shapes of the transform passes (complex elements per y-pass block,
 // y rows per inverse-x block, columns per z-pass block)
 #ifndef DPLR_FFTY_ELEMS
-#define DPLR_FFTY_ELEMS 2048
+#define DPLR_FFTY_ELEMS 4096
 #endif
 #ifndef DPLR_IFFTX_ROWS
 #define DPLR_IFFTX_ROWS 16
@@ -103,7 +113,7 @@ struct dplr_lr_plan_s {
   int* bin_hist = nullptr;    // [max chunks][nbins]
   unsigned* qmax = nullptr;   // max |q| bits: per sort chunk, or one word (global-atomic sort)
   bool block_hist = false;    // bins fit in LDS: sort without global atomics
-  int max_chunks = 256;
+  int max_chunks = DPLR_SORT_CHUNKS;
   void* sorted = nullptr;
   int* perm = nullptr;
   int* sidx = nullptr;
@@ -266,8 +276,11 @@ bool choose_geometry(dplr_lr_plan p) {
 
   // y pass: blocks of zb contiguous rows, about 1024 complex elements
   g.zb = std::max(1, std::min(Kz, DPLR_FFTY_ELEMS / Ky));
-  while (g.zb > 1 && (size_t)g.zb * (padded_len(Ky) + 1) * cs + twb > budget) g.zb /= 2;
+  while (g.zb > 1 && ((size_t)g.zb * (padded_len(Ky) + 1) * cs + twb > budget ||
+                      round_threads((long)g.zb * Ky) > kFftyThreads))
+    g.zb /= 2;
   p->thr_ffty = round_threads((long)g.zb * Ky);
+  if (p->thr_ffty > kFftyThreads) return false;
   // the inverse pass also hosts the final reduction: 7 doubles per thread
   p->lds_ffty = std::max((size_t)g.zb * (padded_len(Ky) + 1) * cs + twb, (size_t)7 * p->thr_ffty * sizeof(double));
 
@@ -354,8 +367,9 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
 
   int nqpart = 1;  // charge-maximum words the spread reads
   if (p->block_hist) {
-    // chunk size: multiple of 1024, at most max_chunks chunks
-    int64_t chunk = std::max<int64_t>(1024, ((n + p->max_chunks - 1) / p->max_chunks + 1023) / 1024 * 1024);
+    // chunk size: a multiple of DPLR_SORT_CHUNK_ALIGN, at most max_chunks chunks
+    constexpr int64_t ca = DPLR_SORT_CHUNK_ALIGN;
+    int64_t chunk = std::max<int64_t>(ca, ((n + p->max_chunks - 1) / p->max_chunks + ca - 1) / ca * ca);
     const int nblk = (int)((n + chunk - 1) / chunk);
     const size_t lds = sizeof(int) * g.nbins;
     if (n > 0) {

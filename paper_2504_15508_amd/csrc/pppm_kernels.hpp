@@ -51,6 +51,7 @@ struct PoissonConsts {
 };
 
 constexpr int kEPT = 16;  // FFT elements per thread bound
+constexpr int kFftyThreads = 256;  // launch bound of the y pass
 
 // Copies n contiguous elements from global memory to LDS with U loads in
 // flight per thread before any of them is stored (a loop whose trip count
@@ -810,7 +811,7 @@ __device__ void reduce_partials(const double* __restrict__ partials, int nblk, d
 }
 
 template <typename T, bool INV>
-__global__ void __launch_bounds__(256) k_ffty(cpx<T>* __restrict__ data, const cpx<T>* __restrict__ twg, Geo g,
+__global__ void __launch_bounds__(kFftyThreads) k_ffty(cpx<T>* __restrict__ data, const cpx<T>* __restrict__ twg, Geo g,
                                               int nsum, size_t sum_stride,
                                               const double* __restrict__ partials, double pre,
                                               double* __restrict__ energy, double* __restrict__ virial) {
