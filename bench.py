@@ -81,6 +81,9 @@ def kernel_bytes(stage: str, N: int, K: int, order: int) -> float:
         return 2 * 3 * spec
     if stage == "ifftx":
         return 3 * spec + 3 * 4 * K ** 3
+    if stage == "ifft_xy_reduce":
+        # three field spectra in, interleaved real fields out
+        return 3 * spec + 3 * 4 * K ** 3
     if stage == "gather":
         # fields read once + particles (d, q, stencil start, perm) + forces
         return 3 * 4 * K ** 3 + part + N * 4 + N * 12
@@ -90,7 +93,7 @@ def kernel_bytes(stage: str, N: int, K: int, order: int) -> float:
 # kernel-name prefix -> stage name of the library instrumentation
 KERNEL_STAGES = [("k_spread_xy", "spread_xy"), ("k_spread_fftx", "spread_fftx"), ("k_ffty<float, false>", "ffty_fwd"),
                  ("k_fftz_poisson", "fftz_poisson"), ("k_ffty<float, true>", "ffty_inv_reduce"),
-                 ("k_ifftx", "ifftx"), ("k_gather", "gather"), ("k_bin_hist", "bin_count"),
+                 ("k_ifftx", "ifftx"), ("k_ifft_xy", "ifft_xy_reduce"), ("k_gather", "gather"), ("k_bin_hist", "bin_count"),
                  ("k_bin_place", "bin_scatter"), ("k_bin_colscan", "bin_scan"), ("k_bin_totscan", "bin_scan")]
 
 

@@ -50,6 +50,9 @@ static_assert(DPLR_SORT_CHUNKS >= 1 && DPLR_SORT_CHUNKS <= 256, "sort chunk coun
 #ifndef DPLR_IFFTX_ROWS
 #define DPLR_IFFTX_ROWS 16
 #endif
+#ifndef DPLR_IXY_MIN_THREADS
+#define DPLR_IXY_MIN_THREADS 64
+#endif
 #ifndef DPLR_FFTZ_COLS
 #define DPLR_FFTZ_COLS 8
 #endif
@@ -103,9 +106,10 @@ struct dplr_lr_plan_s {
   double box[3] = {0, 0, 0};
   bool has_box = false;
   size_t lds_budget = 65536;
-  size_t lds_spread = 0, lds_ffty = 0, lds_z = 0, lds_ifftx = 0;
+  size_t lds_spread = 0, lds_ffty = 0, lds_z = 0, lds_ifftx = 0, lds_ixy = 0;
   bool plane = false;         // whole z planes fit in LDS: spread + x and y transforms in one kernel
-  int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_ifftx = 256;
+  bool ixy = false;           // inverse y and x transforms of a plane component in one kernel
+  int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_ifftx = 256, thr_ixy = 256;
   // device workspace
   int* bin_count = nullptr;
   int* bin_start = nullptr;
@@ -138,8 +142,9 @@ struct dplr_lr_plan_s {
 namespace {
 
 const char* const kStageNames[] = {"bin_count", "bin_scan", "bin_scatter", "spread_fftx", "ffty_fwd",
-                                   "fftz_poisson", "ffty_inv_reduce", "ifftx", "gather", "spread_xy"};
-constexpr int kNumStages = 10;
+                                   "fftz_poisson", "ffty_inv_reduce", "ifftx", "gather", "spread_xy",
+                                   "ifft_xy_reduce"};
+constexpr int kNumStages = 11;
 
 hipEvent_t prof_event(dplr_lr_plan p) {
   if (!p->prof_pool.empty()) {
@@ -291,6 +296,20 @@ bool choose_geometry(dplr_lr_plan p) {
   p->thr_z = round_threads((long)3 * g.yb * Kz);
   g.nzblk = g.Kh * (Ky / g.yb);
   g.zgroup = std::max<int>(1, (int)(128 / (g.yb * cs)));
+
+  // fused inverse y + x pass (plane mode): one block per (z plane, component)
+  p->ixy = false;
+  if (p->plane && Kz % 8 == 0) {
+    const long e_y = (long)g.Kh * Ky, e_x = (long)(Ky / 2) * Kx;
+    const int thr = std::max(DPLR_IXY_MIN_THREADS, (int)(((std::max(e_y, e_x) + kEPT - 1) / kEPT + 63) / 64 * 64));
+    const size_t b_y = (size_t)g.Kh * (padded_len(Ky) + 1) * cs, b_x = (size_t)(Ky / 2) * (padded_len(Kx) + 1) * cs;
+    const size_t lds = std::max(std::max(b_y, b_x) + twb, (size_t)7 * thr * sizeof(double));
+    if (thr <= 1024 && lds <= budget) {
+      p->ixy = true;
+      p->thr_ixy = thr;
+      p->lds_ixy = lds;
+    }
+  }
   return true;
 }
 
@@ -347,6 +366,7 @@ void set_lds_attrs(dplr_lr_plan p) {
   attr((const void*)k_ffty<T, true>, p->lds_ffty);
   attr((const void*)k_fftz_poisson<T>, p->lds_z);
   attr((const void*)k_ifftx<T>, p->lds_ifftx);
+  if (p->ixy) attr((const void*)k_ifft_xy<T>, p->lds_ixy);
 }
 
 template <typename T, int P>
@@ -440,14 +460,19 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
   }
   const double V = p->box[0] * p->box[1] * p->box[2];
   const bool want_virial = !(p->cfg.flags & DPLR_LR_NO_VIRIAL) && virial;
-  {
+  if (p->ixy) {
+    ProfScope ps(p, 10);
+    hipLaunchKernelGGL((k_ifft_xy<T>), dim3(3 * g.K[2]), dim3(p->thr_ixy), p->lds_ixy, s, fspec,
+                       reinterpret_cast<T*>(p->field), tw, g, (const double*)p->partials,
+                       p->cfg.coulomb_k / (2.0 * V), energy, want_virial ? virial : (double*)nullptr);
+  } else {
     ProfScope ps(p, 6);
     hipLaunchKernelGGL((k_ffty<T, true>), dim3(3 * g.Kh * (g.K[2] / g.zb)), dim3(p->thr_ffty), p->lds_ffty, s,
                        fspec, tw, g, 1, (size_t)0, (const double*)p->partials, p->cfg.coulomb_k / (2.0 * V), energy,
                        want_virial ? virial : (double*)nullptr);
   }
   if (n > 0) {
-    {
+    if (!p->ixy) {
       ProfScope ps(p, 7);
       hipLaunchKernelGGL((k_ifftx<T>), dim3(g.K[2] * (g.K[1] / g.xyb)), dim3(p->thr_ifftx), p->lds_ifftx, s, fspec,
                          reinterpret_cast<F3<T>*>(p->field), tw, g);

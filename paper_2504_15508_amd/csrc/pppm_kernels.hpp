@@ -799,8 +799,11 @@ __device__ void reduce_partials(const double* __restrict__ partials, int nblk, d
     red[c * nt + t] = a;
   }
   __syncthreads();
-  for (int h = nt >> 1; h > 0; h >>= 1) {
-    if (t < h) {
+  // pairwise tree over the next power of two (any block size)
+  int top = 1;
+  while (top < nt) top <<= 1;
+  for (int h = top >> 1; h > 0; h >>= 1) {
+    if (t < h && t + h < nt) {
 #pragma unroll
       for (int c = 0; c < 7; ++c) red[c * nt + t] += red[c * nt + t + h];
     }
@@ -1065,6 +1068,105 @@ __global__ void __launch_bounds__(512) k_ifftx(const cpx<T>* __restrict__ fspec,
       v[a] = tr[2 * imul(r >> 1, RS) + col + (r & 1)];
     }
     out[e] = F3<T>{v[0], v[1], v[2]};
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Inverse y and x transforms of one field component on one z plane (used when
+// a plane fits in LDS; it replaces the separate inverse y and x passes).  The
+// Kh rows (kx, z) of the component's spectrum are transformed along y, then
+// recombined into complex pairs of real x rows: row pair (2c, 2c+1) takes
+// A + iB for kx <= Kx/2 and conj(A) + i conj(B) at Kx - kx (Hermitian
+// symmetry), with the imaginary parts of the kx = 0 and Kx/2 terms dropped.
+// One inverse complex FFT per pair along x gives both real rows, written as
+// component a of the interleaved field records.  Block b serves plane
+// z = 8 (b / 24) + b % 8 and component (b / 8) % 3, so the three components of a
+// plane land on the same XCD (blocks are dealt round-robin over 8 XCDs) and
+// its L2 merges their partial record writes.  Block 0 also performs the final
+// energy/virial reduction.
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024) k_ifft_xy(const cpx<T>* __restrict__ fspec, T* __restrict__ field,
+                                                  const cpx<T>* __restrict__ twg, Geo g,
+                                                  const double* __restrict__ partials, double pre,
+                                                  double* __restrict__ energy, double* __restrict__ virial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2], Kh = g.Kh;
+  const int RS = padded_len(Kx) + 1;  // x rows (complex pairs of real rows)
+  const int RY = padded_len(Ky) + 1;  // y rows ([kx][y])
+  cpx<T>* ty = reinterpret_cast<cpx<T>*>(smem);  // [Kh][RY]
+  cpx<T>* tx = reinterpret_cast<cpx<T>*>(smem);  // [Ky/2][RS]
+  const size_t b_ty = (size_t)Kh * RY * sizeof(cpx<T>);
+  const size_t b_tx = (size_t)(Ky / 2) * RS * sizeof(cpx<T>);
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem + max(b_ty, b_tx));
+  const int zx = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int zg = slot / 3, a = slot - 3 * zg;
+  const int z = zg * 8 + zx;
+  const int lkx = 31 - __clz(Kx), lky = 31 - __clz(Ky);
+  copy_g2s<8>(tw, twg, g.twN);
+
+  // rows (kx, z) of component a: Ky contiguous values each, Kz * Ky apart
+  constexpr int kMax = 16;  // host: Kh * Ky <= 16 * blockDim.x
+  {
+    const cpx<T>* src = fspec + (size_t)a * Kh * Kz * Ky + (size_t)z * Ky;
+    const size_t rstride = (size_t)Kz * Ky;
+    cpx<T> r[kMax];
+#pragma unroll
+    for (int c = 0; c < kMax; ++c) {
+      const int e = threadIdx.x + c * blockDim.x;
+      if (e < Kh * Ky) r[c] = src[(size_t)(e >> lky) * rstride + (e & (Ky - 1))];
+    }
+#pragma unroll
+    for (int c = 0; c < kMax; ++c) {
+      const int e = threadIdx.x + c * blockDim.x;
+      if (e < Kh * Ky) ty[imul(e >> lky, RY) + lds_pad(e & (Ky - 1))] = r[c];
+    }
+  }
+  __syncthreads();
+  fft_rows<T, true, kEPT, true>(ty, Kh, Ky, RY, 1, false, tw, g.twN);
+
+  // [kx][y] -> complex row pairs along x, in place through registers
+  {
+    const int half = Ky >> 1, lhalf = lky - 1;
+    constexpr int kPairs = kMax / 2;  // Kh * Ky / 2 <= 8 * blockDim.x
+    cpx<T> A[kPairs], B[kPairs];
+#pragma unroll
+    for (int c = 0; c < kPairs; ++c) {
+      const int i = threadIdx.x + c * blockDim.x;  // i = kx * (Ky/2) + pair
+      if (i < Kh * half) {
+        const int k = i >> lhalf, pr = i & (half - 1);
+        const cpx<T>* row = ty + imul(k, RY);
+        A[c] = row[lds_pad(2 * pr)];
+        B[c] = row[lds_pad(2 * pr + 1)];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kPairs; ++c) {
+      const int i = threadIdx.x + c * blockDim.x;
+      if (i < Kh * half) {
+        const int k = i >> lhalf, pr = i & (half - 1);
+        cpx<T> av = A[c], bv = B[c];
+        if (k == 0 || k == Kx / 2) { av.y = (T)0; bv.y = (T)0; }
+        cpx<T>* zr = tx + imul(pr, RS);
+        zr[lds_pad(k)] = cpx<T>{av.x - bv.y, av.y + bv.x};
+        if (k > 0 && k < Kx / 2) zr[lds_pad(Kx - k)] = cpx<T>{av.x + bv.y, bv.x - av.y};
+      }
+    }
+  }
+  __syncthreads();
+  fft_rows<T, true, kEPT, true>(tx, Ky / 2, Kx, RS, 1, false, tw, g.twN);
+
+  // real rows: y even in the real parts, y odd in the imaginary parts
+  const T* tr = reinterpret_cast<const T*>(tx);
+  T* out = field + (size_t)z * Ky * Kx * 3 + a;
+  for (int e = threadIdx.x; e < Ky * Kx; e += blockDim.x) {
+    const int y = e >> lkx, x = e & (Kx - 1);
+    out[(size_t)e * 3] = tr[2 * (imul(y >> 1, RS) + lds_pad(x)) + (y & 1)];
+  }
+  if (energy && blockIdx.x == 0) {
+    __syncthreads();
+    reduce_partials(partials, g.nzblk, pre, energy, virial, reinterpret_cast<double*>(smem));
   }
 }
 
