@@ -356,16 +356,22 @@ struct Ranges {
   int b[48][2]; // scratch: bin bounds, then particle bounds, per candidate range
 };
 
-// Called by every thread of the block (contains barriers).  Each candidate
-// range (up to two per plane) is resolved by its own thread, so the block
-// waits for one round of bin_start loads instead of a chain of them.
-__device__ __forceinline__ void build_ranges(Ranges& R, const int* __restrict__ bin_start, const Geo& g,
-                                             int xsplit, int z_lo, int nplanes, int q_lo, int nq) {
+// Candidate ranges (up to two per plane) are resolved one per thread, so the
+// block waits for one round of bin_start loads instead of a chain of them.
+// range_load issues the loads (no barrier); ranges_finish stores them, then
+// thread 0 lists the non-empty ranges, merging ranges that continue each
+// other in the sorted order (consecutive planes usually do).
+struct RangeLoad {
+  int ncand, b0, b1;
+};
+
+__device__ __forceinline__ RangeLoad range_load(const int* __restrict__ bin_start, const Geo& g, int xsplit,
+                                                int z_lo, int nplanes, int q_lo, int nq) {
   const int t = threadIdx.x;
   const int qa = wrapi(q_lo, g.NQ);
   const bool split = qa + nq > g.NQ;
-  const int ncand = nplanes * (split ? 2 : 1);
-  if (t < ncand) {
+  RangeLoad L{nplanes * (split ? 2 : 1), 0, 0};
+  if (t < L.ncand) {
     const int i = split ? (t >> 1) : t, j = split ? (t & 1) : 0;
     const int z = wrapi(z_lo + i, g.K[2]);
     int q0, q1;
@@ -373,25 +379,44 @@ __device__ __forceinline__ void build_ranges(Ranges& R, const int* __restrict__ 
     else if (j == 0) { q0 = qa; q1 = g.NQ; }
     else { q0 = 0; q1 = qa + nq - g.NQ; }
     const int b0 = (xsplit * g.K[2] + z) * g.NQ;
-    R.b[t][0] = bin_start[b0 + q0];
-    R.b[t][1] = bin_start[b0 + q1];
+    L.b0 = bin_start[b0 + q0];
+    L.b1 = bin_start[b0 + q1];
+  }
+  return L;
+}
+
+// Called by every thread of the block (contains barriers).
+__device__ __forceinline__ void ranges_finish(Ranges& R, const RangeLoad& L) {
+  const int t = threadIdx.x;
+  if (t < L.ncand) {
+    R.b[t][0] = L.b0;
+    R.b[t][1] = L.b1;
   }
   __syncthreads();
   if (t == 0) {
     int n = 0, acc = 0;
-    for (int c = 0; c < ncand; ++c) {
+    for (int c = 0; c < L.ncand; ++c) {
       const int p0 = R.b[c][0], p1 = R.b[c][1];
       if (p1 > p0) {
-        R.lo[n] = p0;
-        R.pre[n] = acc;
-        acc += p1 - p0;
-        ++n;
+        if (n > 0 && R.lo[n - 1] + (acc - R.pre[n - 1]) == p0) {
+          acc += p1 - p0;  // continues the previous range
+        } else {
+          R.lo[n] = p0;
+          R.pre[n] = acc;
+          acc += p1 - p0;
+          ++n;
+        }
       }
     }
     R.pre[n] = acc;
     R.n = n;
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void build_ranges(Ranges& R, const int* __restrict__ bin_start, const Geo& g,
+                                             int xsplit, int z_lo, int nplanes, int q_lo, int nq) {
+  ranges_finish(R, range_load(bin_start, g, xsplit, z_lo, nplanes, q_lo, nq));
 }
 
 __device__ __forceinline__ int range_index(const Ranges& R, int v) {
@@ -639,17 +664,24 @@ __global__ void __launch_bounds__(1024) k_spread_xy(const T4<T>* __restrict__ so
   __shared__ unsigned qm_s;
 
   const int z = blockIdx.x % Kz, split = blockIdx.x / Kz;
+  // global loads first (range bounds, charge maxima), so that their latencies
+  // overlap each other and the clearing of the accumulators
+  const RangeLoad rl = range_load(bin_start, g, split, z - (P - 1), min(P, Kz), 0, g.NQ);
+  unsigned qb = 0u;
+  if constexpr (sizeof(T) == 4) {
+    for (int i = threadIdx.x; i < nqpart; i += blockDim.x) qb = max(qb, qmax_part[i]);
+  }
   if (threadIdx.x == 0) qm_s = 0u;
   for (int e = threadIdx.x; e < Ky * RX; e += blockDim.x) acc[e] = 0;
   copy_g2s<8>(tw, twg, g.twN);
-  build_ranges(R, bin_start, g, split, z - (P - 1), min(P, Kz), 0, g.NQ);  // contains barriers
+  if constexpr (sizeof(T) == 4) {
+    qb = wave_max_u32(qb);
+    __syncthreads();  // qm_s initialised
+    if ((threadIdx.x & 63) == 0 && qb) atomicMax(&qm_s, qb);
+  }
+  ranges_finish(R, rl);  // contains barriers (also publishes qm_s)
   T scale;
   if constexpr (sizeof(T) == 4) {
-    unsigned qb = 0u;
-    for (int i = threadIdx.x; i < nqpart; i += blockDim.x) qb = max(qb, qmax_part[i]);
-    qb = wave_max_u32(qb);
-    if ((threadIdx.x & 63) == 0 && qb) atomicMax(&qm_s, qb);
-    __syncthreads();
     scale = fixed_scale_fp32(qm_s);
   } else {
     scale = (T)1099511627776.0;  // 2^40
