@@ -1,11 +1,13 @@
 """Writes the stored Ewald reference values used by the full-size GPU tests.
 
-Calls only the oracle (oracle/ewald.c through oracle/ewald.py) on the seeded
-synthetic systems of the `systems` package, at the FP32-rounded coordinates
-the FP32 kernels receive.  Output: tests/golden/ewald_<workload>.json with the
+Calls only the oracle (oracle/ewald.c through oracle/ewald.py, and the PPPM
+oracle oracle/pppm.py) on the seeded synthetic systems of the `systems`
+package, at the FP32-rounded coordinates the FP32 kernels receive.  Output:
+tests/golden/ewald_<workload>.json (FP64 Ewald) or
+tests/golden/pppm_<workload>_<mesh>_p<order>.json (FP64 PPPM oracle) with the
 energy, the virial and the forces on a seeded sample of particles.
 
-    python tests/golden/make_golden.py [workload_index ...]
+    python tests/golden/make_golden.py [workload_index | fd | pppm:<index>:<mesh>:<order> ...]
 """
 import json
 import os
@@ -18,7 +20,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import systems  # noqa: E402
-from oracle import ewald  # noqa: E402
+from oracle import ewald, pppm  # noqa: E402
 
 SAMPLE = 2048
 SAMPLE_SEED = 4242
@@ -80,10 +82,36 @@ def make_fd(k: int = 2):
     print(f"{path}: {time.time() - t:.1f}s", flush=True)
 
 
+def make_pppm(k: int, mesh: int, order: int, alias: int = 2):
+    """FP64 PPPM oracle (ik differentiation, alias range |m| <= alias) at mesh^3:
+    energy, virial and the forces on the same seeded sample as make()."""
+    w = systems.workload(k)
+    s = w.system().rounded(np.float32)
+    idx = np.sort(np.random.default_rng(SAMPLE_SEED).choice(s.n, size=min(SAMPLE, s.n), replace=False))
+    t = time.time()
+    e, f, vir = pppm.pppm(s.all_pos(), s.all_q(), s.box, (mesh,) * 3, order, w.beta, w.coulomb_k, alias)
+    dt = time.time() - t
+    out = {
+        "workload": w.name, "n_ion": s.n_ion, "n_wc": s.n_wc, "box": s.box.tolist(),
+        "beta": w.beta, "coulomb_k": w.coulomb_k, "positions": "float32-rounded",
+        "mesh": mesh, "order": order, "alias": alias, "energy": e, "virial": np.asarray(vir).tolist(),
+        "sample_seed": SAMPLE_SEED, "sample_index": idx.tolist(), "sample_force": f[idx].tolist(),
+        "oracle_seconds": dt,
+        "generator": "tests/golden/make_golden.py pppm (oracle/pppm.py, FP64 PPPM-ik)",
+    }
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"pppm_{w.name}_{mesh}_p{order}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh)
+    print(f"{path}: E={e:.12g} in {dt:.1f}s", flush=True)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:] or ["3"]
     for a in args:
         if a == "fd":
             make_fd(2)
+        elif a.startswith("pppm:"):
+            _, k, mesh, order = a.split(":")
+            make_pppm(int(k), int(mesh), int(order))
         else:
             make(int(a))
