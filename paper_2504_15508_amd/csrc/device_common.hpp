@@ -351,27 +351,53 @@ __device__ __forceinline__ void fft_rows(cpx<T>* buf, int nrows, int N, int rstr
 // B-spline assignment.  For mesh coordinate u (in mesh units) the stencil is
 // the P points g = s .. s+P-1 with s = floor(u - P/2) + 1, and the weight of
 // point s+t is M_P(u - (s+t) + P/2) = M_P(d + P-1-t), d = u - P/2 - floor(u - P/2).
-// The values M_P(d + i), i = 0..P-1, are built order by order with the
-// B-spline recursion M_k(x) = [x M_{k-1}(x) + (k-x) M_{k-1}(x-1)] / (k-1).
+// On [0, 1) each M_P(d + i), i = 0..P-1, is a polynomial of degree P-1 in d.
+// Its coefficients follow from the B-spline recursion
+// M_k(x) = [x M_{k-1}(x) + (k-x) M_{k-1}(x-1)] / (k-1), applied to coefficient
+// arrays at compile time; a weight is then P-1 fused multiply-adds (Horner)
+// instead of the O(P^2) recursion per coordinate.
 // ---------------------------------------------------------------------------
+template <int P>
+struct BsplineCoeffs {
+  double c[P][P];  // c[i][j]: coefficient of d^j in M_P(d + i), 0 <= d < 1
+  constexpr BsplineCoeffs() : c{} {
+    double m[P][P] = {};  // M_k(d + i) for the current order k
+    m[0][0] = 1.0;        // M_1(d) = 1
+    for (int k = 2; k <= P; ++k) {
+      double nm[P][P] = {};
+      for (int i = 0; i < k; ++i) {
+        for (int j = 0; j < P; ++j) {
+          double v = 0.0;
+          if (i <= k - 2) {  // (d + i) M_{k-1}(d + i)
+            v += i * m[i][j];
+            if (j > 0) v += m[i][j - 1];
+          }
+          if (i >= 1) {  // (k - i - d) M_{k-1}(d + i - 1)
+            v += (k - i) * m[i - 1][j];
+            if (j > 0) v -= m[i - 1][j - 1];
+          }
+          nm[i][j] = v / (k - 1);
+        }
+      }
+      for (int i = 0; i < P; ++i)
+        for (int j = 0; j < P; ++j) m[i][j] = nm[i][j];
+    }
+    for (int i = 0; i < P; ++i)
+      for (int j = 0; j < P; ++j) c[i][j] = m[i][j];
+  }
+};
+
 template <typename T, int P>
 __device__ __forceinline__ void bspline_weights(T d, T* w) {
-  T m[P];
-  m[0] = (T)1;
+  constexpr BsplineCoeffs<P> C{};
 #pragma unroll
-  for (int i = 1; i < P; ++i) m[i] = (T)0;
+  for (int t = 0; t < P; ++t) {
+    const int i = P - 1 - t;
+    T v = (T)C.c[i][P - 1];
 #pragma unroll
-  for (int k = 2; k <= P; ++k) {
-    const T inv = (T)1 / (T)(k - 1);
-#pragma unroll
-    for (int i = k - 1; i >= 0; --i) {
-      const T a = (i <= k - 2) ? m[i] : (T)0;
-      const T b = (i >= 1) ? m[i - 1] : (T)0;
-      m[i] = ((d + (T)i) * a + ((T)k - d - (T)i) * b) * inv;
-    }
+    for (int j = P - 2; j >= 0; --j) v = v * d + (T)C.c[i][j];
+    w[t] = v;
   }
-#pragma unroll
-  for (int t = 0; t < P; ++t) w[t] = m[P - 1 - t];
 }
 
 }  // namespace dplr
