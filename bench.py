@@ -94,7 +94,7 @@ def kernel_bytes(stage: str, N: int, K: int, order: int) -> float:
 KERNEL_STAGES = [("k_spread_xy", "spread_xy"), ("k_spread_fftx", "spread_fftx"), ("k_ffty<float, false>", "ffty_fwd"),
                  ("k_fftz_poisson", "fftz_poisson"), ("k_ffty<float, true>", "ffty_inv_reduce"),
                  ("k_ifftx", "ifftx"), ("k_ifft_xy", "ifft_xy_reduce"), ("k_gather", "gather"), ("k_bin_hist", "bin_count"),
-                 ("k_bin_place", "bin_scatter"), ("k_bin_colscan", "bin_scan"), ("k_bin_totscan", "bin_scan")]
+                 ("k_bin_place", "bin_scatter"), ("k_bin_colscan", "bin_scan")]
 
 
 def ingest_counters(fetch_csv: str, write_csv: str, copy_mb: float) -> dict:

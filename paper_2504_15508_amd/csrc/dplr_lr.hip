@@ -341,8 +341,10 @@ void free_all(dplr_lr_plan p) {
 template <typename T>
 void set_lds_attrs(dplr_lr_plan p) {
   // kernels whose dynamic LDS can exceed the 64 KiB default
+  // a refusal is cleared here: a kernel that needed it then fails at its own launch
   auto attr = [&](const void* f, size_t b) {
-    if (b > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+    if (b > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b) != hipSuccess)
+      (void)hipGetLastError();
   };
   switch (p->cfg.order) {
 #define DPLR_ATTR(PP)                                                        \
@@ -353,11 +355,12 @@ void set_lds_attrs(dplr_lr_plan p) {
     DPLR_ATTR(2) DPLR_ATTR(3) DPLR_ATTR(4) DPLR_ATTR(5) DPLR_ATTR(6) DPLR_ATTR(7) DPLR_ATTR(8)
 #undef DPLR_ATTR
   }
-  switch (p->cfg.order) {
+  // LDS histograms and placement ranks: only when the bins fit (block_hist)
+  if (p->block_hist) switch (p->cfg.order) {
 #define DPLR_ATTR2(PP)                                                                   \
   case PP:                                                                               \
     attr((const void*)k_bin_hist<T, PP>, sizeof(int) * (size_t)p->geo.nbins);           \
-    attr((const void*)k_bin_place<T, PP>, sizeof(int) * (size_t)p->geo.nbins);          \
+    attr((const void*)k_bin_place<T, PP>, 2 * sizeof(int) * (size_t)p->geo.nbins);      \
     break;
     DPLR_ATTR2(2) DPLR_ATTR2(3) DPLR_ATTR2(4) DPLR_ATTR2(5) DPLR_ATTR2(6) DPLR_ATTR2(7) DPLR_ATTR2(8)
 #undef DPLR_ATTR2
@@ -399,19 +402,20 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
     }
     {
       ProfScope ps(p, 1);
+      // per-bin chunk offsets and bin totals; the placement scans the totals
       if (n > 0) {
         hipLaunchKernelGGL(k_bin_colscan, dim3((g.nbins + 63) / 64), dim3(1024), 0, s, p->bin_hist, p->bin_count,
                            nblk, g.nbins);
       } else {
-        hipLaunchKernelGGL(k_fill_int, dim3((g.nbins + 255) / 256), dim3(256), 0, s, p->bin_count, g.nbins, 0);
+        hipLaunchKernelGGL(k_fill_int, dim3((g.nbins + 1 + 255) / 256), dim3(256), 0, s, p->bin_start, g.nbins + 1,
+                           0);
       }
-      hipLaunchKernelGGL(k_bin_totscan, dim3(1), dim3(1024), 0, s, p->bin_count, p->bin_start, g.nbins);
     }
     if (n > 0) {
       ProfScope ps(p, 2);
-      hipLaunchKernelGGL((k_bin_place<T, P>), dim3(nblk), dim3(1024), lds, s, ip, wp, (const T*)ion_q,
-                         (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], p->bin_hist, p->bin_start, sorted, p->sidx,
-                         p->perm, p->qmax, (int)chunk, g);
+      hipLaunchKernelGGL((k_bin_place<T, P>), dim3(nblk), dim3(1024), 2 * lds, s, ip, wp, (const T*)ion_q,
+                         (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], p->bin_hist, p->bin_count, p->bin_start,
+                         sorted, p->sidx, p->perm, p->qmax, (int)chunk, g);
     }
     nqpart = n > 0 ? nblk : 0;
   } else {

@@ -223,8 +223,9 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const T* __restrict__ ion_p
 // Particles are cut into chunks of `chunk` consecutive indices; chunk c's
 // histogram is built with LDS atomics and stored densely in hist[c][bin];
 // a per-bin scan over chunks turns it into the chunk's offset inside the bin,
-// a scan over bins gives bin_start, and the scatter places particle i of
-// chunk c at bin_start[bin] + hist[c][bin] + (its rank within the chunk).
+// a scan over bins (inside the placement kernel) gives bin_start, and the
+// scatter places particle i of chunk c at
+// bin_start[bin] + hist[c][bin] + (its rank within the chunk).
 template <typename T, int P>
 __global__ void __launch_bounds__(1024) k_bin_hist(const T* __restrict__ ion_pos, const T* __restrict__ wc_pos,
                                                    int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
@@ -284,44 +285,67 @@ __global__ void __launch_bounds__(1024) k_bin_colscan(int* __restrict__ hist, in
   }
 }
 
-// Exclusive scan of the bin totals (one block of 1024 threads).
-__global__ void __launch_bounds__(1024) k_bin_totscan(const int* __restrict__ total, int* __restrict__ start,
-                                                      int nbins) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int chunk = (nbins + nt - 1) / nt;
-  const int b0 = min(nbins, t * chunk), b1 = min(nbins, b0 + chunk);
+// Exclusive scan of v[0, n) (global) into out[0, n) (LDS) by the whole block,
+// one contiguous stretch of bins per thread; returns the total.  wsum: 17
+// ints of LDS.
+__device__ __forceinline__ int block_exclusive_scan(const int* __restrict__ v, int* out, int n, int* wsum) {
+  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, w = t >> 6, nw = nt >> 6;
+  const int per = (n + nt - 1) / nt;
+  const int b0 = min(n, t * per), b1 = min(n, b0 + per);
   int s = 0;
-  for (int b = b0; b < b1; ++b) s += total[b];
-  part[t] = s;
+  for (int b = b0; b < b1; ++b) s += v[b];
+  int x = s;  // inclusive scan within the wave
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
   __syncthreads();
-  for (int off = 1; off < nt; off <<= 1) {
-    int v = (t >= off) ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  if (w == 0) {
+    const int ws = lane < nw ? wsum[lane] : 0;
+    int xs = ws;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(xs, off, 64);
+      if (lane >= off) xs += y;
+    }
+    if (lane < nw) wsum[lane] = xs - ws;
+    if (lane == nw - 1) wsum[16] = xs;
   }
-  int run = part[t] - s;
+  __syncthreads();
+  int run = wsum[w] + x - s;
   for (int b = b0; b < b1; ++b) {
-    start[b] = run;
-    run += total[b];
+    out[b] = run;
+    run += v[b];
   }
-  if (t == nt - 1) start[nbins] = part[t];
+  return wsum[16];
 }
 
+// Placement.  Every block first turns the bin totals into bin starts (an
+// exclusive scan in LDS; block 0 also publishes them as bin_start), then
+// scatters its chunk.
 template <typename T, int P>
 __global__ void __launch_bounds__(1024) k_bin_place(const T* __restrict__ ion_pos, const T* __restrict__ wc_pos,
                                                     const T* __restrict__ ion_q, const T* __restrict__ wc_q,
                                                     int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
-                                                    const int* __restrict__ hist, const int* __restrict__ start,
+                                                    const int* __restrict__ hist, const int* __restrict__ total,
+                                                    int* __restrict__ bin_start,
                                                     T4<T>* __restrict__ sorted, int* __restrict__ sidx,
                                                     int* __restrict__ perm, unsigned* __restrict__ qmax_part,
                                                     int chunk, Geo g) {
-  extern __shared__ int lc[];
+  extern __shared__ int lc[];  // [nbins] ranks, then [nbins] bin starts
+  int* start = lc + g.nbins;
   __shared__ unsigned qm;
+  __shared__ int wsum[17];
   for (int b = threadIdx.x; b < g.nbins; b += blockDim.x) lc[b] = 0;
   if (threadIdx.x == 0) qm = 0u;
+  const int all = block_exclusive_scan(total, start, g.nbins, wsum);  // contains barriers
   __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int b = threadIdx.x; b < g.nbins; b += blockDim.x) bin_start[b] = start[b];
+    if (threadIdx.x == 0) bin_start[g.nbins] = all;
+  }
   unsigned qb = 0u;
   const double invh[3] = {ihx, ihy, ihz};
   const int64_t i0 = (int64_t)blockIdx.x * chunk;
