@@ -134,9 +134,14 @@ __device__ __forceinline__ void dft_l(cpx<T>* v) {
 // whether consecutive threads walk rows (column layouts) or the L threads of
 // one row.  Every thread of the block must call it (it synchronises).
 // ---------------------------------------------------------------------------
-template <typename T, int L, bool INV, bool PAD>
-__device__ __forceinline__ void fft_rows_reg(cpx<T>* buf, int nrows, int rstride, int estride, bool rows_fast,
-                                             const cpx<T>* tw, int twN) {
+// The first read phase takes its inputs from load(r, e) and the last write
+// phase hands its outputs to store(r, e, value), so a caller can fuse a
+// conversion or rearrangement into the transform's own passes; the exchange
+// in between goes through buf.  Every read made by load happens before the
+// first barrier, so buf may alias what load reads.
+template <typename T, int L, bool INV, bool PAD, typename LoadF, typename StoreF>
+__device__ __forceinline__ void fft_rows_reg_io(cpx<T>* buf, int nrows, int rstride, int estride, bool rows_fast,
+                                                const cpx<T>* tw, int twN, LoadF load, StoreF store) {
   constexpr int N = 16 * L, J = 16 / L;
   const int t = threadIdx.x;
   const bool act = t < nrows * L;
@@ -152,7 +157,7 @@ __device__ __forceinline__ void fft_rows_reg(cpx<T>* buf, int nrows, int rstride
   if constexpr (!INV) {
     if (act) {
 #pragma unroll
-      for (int n1 = 0; n1 < 16; ++n1) v[n1] = at(l + L * n1);
+      for (int n1 = 0; n1 < 16; ++n1) v[n1] = load(r, l + L * n1);
     }
     __syncthreads();
     if (act) {
@@ -173,7 +178,7 @@ __device__ __forceinline__ void fft_rows_reg(cpx<T>* buf, int nrows, int rstride
       for (int j = 0; j < J; ++j) {
         dft_l<T, L, false>(v + j * L);
 #pragma unroll
-        for (int k2 = 0; k2 < L; ++k2) at(l * J + j + 16 * k2) = v[j * L + k2];
+        for (int k2 = 0; k2 < L; ++k2) store(r, l * J + j + 16 * k2, v[j * L + k2]);
       }
     }
     __syncthreads();
@@ -182,7 +187,7 @@ __device__ __forceinline__ void fft_rows_reg(cpx<T>* buf, int nrows, int rstride
 #pragma unroll
       for (int j = 0; j < J; ++j) {
 #pragma unroll
-        for (int k2 = 0; k2 < L; ++k2) v[j * L + k2] = at(l * J + j + 16 * k2);
+        for (int k2 = 0; k2 < L; ++k2) v[j * L + k2] = load(r, l * J + j + 16 * k2);
       }
     }
     __syncthreads();
@@ -210,9 +215,40 @@ __device__ __forceinline__ void fft_rows_reg(cpx<T>* buf, int nrows, int rstride
     if (act) {
       dft16<T, true>(v);
 #pragma unroll
-      for (int n1 = 0; n1 < 16; ++n1) at(l + L * n1) = v[n1];
+      for (int n1 = 0; n1 < 16; ++n1) store(r, l + L * n1, v[n1]);
     }
     __syncthreads();
+  }
+}
+
+template <typename T, int L, bool INV, bool PAD>
+__device__ __forceinline__ void fft_rows_reg(cpx<T>* buf, int nrows, int rstride, int estride, bool rows_fast,
+                                             const cpx<T>* tw, int twN) {
+  auto elem = [=](int r, int e) -> cpx<T>& { return buf[r * rstride + (PAD ? lds_pad(e) : e * estride)]; };
+  fft_rows_reg_io<T, L, INV, PAD>(
+      buf, nrows, rstride, estride, rows_fast, tw, twN, [&](int r, int e) { return elem(r, e); },
+      [&](int r, int e, const cpx<T>& x) { elem(r, e) = x; });
+}
+
+// Row transforms (PAD layout, exchange through buf) with fused input and
+// output: applicable for FP32 rows of N = 16 L <= 256 points when the block
+// has nrows * L threads; false (nothing done) otherwise.
+template <typename T, bool INV, typename LoadF, typename StoreF>
+__device__ __forceinline__ bool fft_rows_io(cpx<T>* buf, int nrows, int N, int rstride, const cpx<T>* tw, int twN,
+                                            LoadF load, StoreF store) {
+  if constexpr (sizeof(T) != 4) {
+    return false;
+  } else {
+    const int L = N / 16;
+    if (N < 16 || N > 256 || nrows * L > (int)blockDim.x) return false;
+    switch (L) {
+      case 1: fft_rows_reg_io<T, 1, INV, true>(buf, nrows, rstride, 1, false, tw, twN, load, store); return true;
+      case 2: fft_rows_reg_io<T, 2, INV, true>(buf, nrows, rstride, 1, false, tw, twN, load, store); return true;
+      case 4: fft_rows_reg_io<T, 4, INV, true>(buf, nrows, rstride, 1, false, tw, twN, load, store); return true;
+      case 8: fft_rows_reg_io<T, 8, INV, true>(buf, nrows, rstride, 1, false, tw, twN, load, store); return true;
+      case 16: fft_rows_reg_io<T, 16, INV, true>(buf, nrows, rstride, 1, false, tw, twN, load, store); return true;
+    }
+    return false;
   }
 }
 

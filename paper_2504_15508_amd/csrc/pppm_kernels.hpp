@@ -753,15 +753,31 @@ __global__ void __launch_bounds__(1024) k_spread_xy(const T4<T>* __restrict__ so
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < Ky * XH; e += blockDim.x) {
-    const int row = e / XH, j = e - row * XH;
-    acc[imul(row, RX) + j] += acc[imul(row, RX) + Kx + j];
-  }
-  __syncthreads();
-
-  // fixed point -> complex row pairs (in place through registers)
   const int lkx = 31 - __clz(Kx), lky = 31 - __clz(Ky);
-  {
+  const double inv_scale = 1.0 / (double)scale;
+  cpx<T>* out = spec + (size_t)split * split_stride;
+
+  // x transform of the row pairs (2r, 2r+1) as complex rows.  The fused form
+  // reads the fixed-point rows directly, folding the x overhang back and
+  // converting on the way in.
+  auto load_x = [&](int r, int e) {
+    const long long* a0 = acc + imul(2 * r, RX);
+    const long long* a1 = a0 + RX;
+    long long v0 = a0[e], v1 = a1[e];
+    if (e < XH) {
+      v0 += a0[Kx + e];
+      v1 += a1[Kx + e];
+    }
+    return cpx<T>{(T)((double)v0 * inv_scale), (T)((double)v1 * inv_scale)};
+  };
+  auto store_tx = [&](int r, int e, const cpx<T>& v) { tx_tile[imul(r, RS) + lds_pad(e)] = v; };
+  if (!fft_rows_io<T, false>(tx_tile, Ky / 2, Kx, RS, tw, g.twN, load_x, store_tx)) {
+    for (int e = threadIdx.x; e < Ky * XH; e += blockDim.x) {
+      const int row = e / XH, j = e - row * XH;
+      acc[imul(row, RX) + j] += acc[imul(row, RX) + Kx + j];
+    }
+    __syncthreads();
+    // fixed point -> complex row pairs (in place through registers)
     constexpr int kMaxPer = 16;
     long long v[kMaxPer];
 #pragma unroll
@@ -770,54 +786,48 @@ __global__ void __launch_bounds__(1024) k_spread_xy(const T4<T>* __restrict__ so
       if (e < Ky * Kx) v[c] = acc[imul(e >> lkx, RX) + (e & (Kx - 1))];
     }
     __syncthreads();
-    const double inv_scale = 1.0 / (double)scale;
-    T* out = reinterpret_cast<T*>(tx_tile);
+    T* o = reinterpret_cast<T*>(tx_tile);
 #pragma unroll
     for (int c = 0; c < kMaxPer; ++c) {
       const int e = threadIdx.x + c * blockDim.x;
       if (e < Ky * Kx) {
         const int row = e >> lkx, x = e & (Kx - 1);
-        out[2 * (imul(row >> 1, RS) + lds_pad(x)) + (row & 1)] = (T)((double)v[c] * inv_scale);
+        o[2 * (imul(row >> 1, RS) + lds_pad(x)) + (row & 1)] = (T)((double)v[c] * inv_scale);
       }
     }
     __syncthreads();
+    fft_rows<T, false, kEPT, true>(tx_tile, Ky / 2, Kx, RS, 1, false, tw, g.twN);
   }
-  fft_rows<T, false, kEPT, true>(tx_tile, Ky / 2, Kx, RS, 1, false, tw, g.twN);
 
-  // separate the two half spectra of every row pair into [kx][y] rows
+  // y transform of the kx rows: the two half spectra of every row pair are
+  // separated on the way in, and the fused form writes the spectrum directly
+  auto load_y = [&](int k, int y) {
+    const cpx<T>* zr = tx_tile + imul(y >> 1, RS);
+    const cpx<T> z1 = zr[lds_pad(k)];
+    const cpx<T> z2 = cconj(zr[lds_pad((Kx - k) & (Kx - 1))]);
+    if ((y & 1) == 0) return cpx<T>{(T)0.5 * (z1.x + z2.x), (T)0.5 * (z1.y + z2.y)};
+    const cpx<T> d = csub(z1, z2);
+    return cpx<T>{(T)0.5 * d.y, (T)-0.5 * d.x};
+  };
+  auto store_spec = [&](int k, int y, const cpx<T>& v) { out[(unsigned)imul(imul(k, Kz) + z, Ky) + y] = v; };
+  if (fft_rows_io<T, false>(ty_tile, Kh, Ky, RY, tw, g.twN, load_y, store_spec)) return;
   {
     constexpr int kMaxOut = 16;
     cpx<T> o[kMaxOut];
 #pragma unroll
     for (int c = 0; c < kMaxOut; ++c) {
       const int e = threadIdx.x + c * blockDim.x;  // e = kx * Ky + y
-      if (e < Kh * Ky) {
-        const int k = e >> lky, y = e & (Ky - 1);
-        const cpx<T>* zr = tx_tile + imul(y >> 1, RS);
-        const cpx<T> z1 = zr[lds_pad(k)];
-        const cpx<T> z2 = cconj(zr[lds_pad((Kx - k) & (Kx - 1))]);
-        if ((y & 1) == 0) {
-          o[c] = cpx<T>{(T)0.5 * (z1.x + z2.x), (T)0.5 * (z1.y + z2.y)};
-        } else {
-          const cpx<T> d = csub(z1, z2);
-          o[c] = cpx<T>{(T)0.5 * d.y, (T)-0.5 * d.x};
-        }
-      }
+      if (e < Kh * Ky) o[c] = load_y(e >> lky, e & (Ky - 1));
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < kMaxOut; ++c) {
       const int e = threadIdx.x + c * blockDim.x;
-      if (e < Kh * Ky) {
-        const int k = e >> lky, y = e & (Ky - 1);
-        ty_tile[imul(k, RY) + lds_pad(y)] = o[c];
-      }
+      if (e < Kh * Ky) ty_tile[imul(e >> lky, RY) + lds_pad(e & (Ky - 1))] = o[c];
     }
     __syncthreads();
   }
   fft_rows<T, false, kEPT, true>(ty_tile, Kh, Ky, RY, 1, false, tw, g.twN);
-
-  cpx<T>* out = spec + (size_t)split * split_stride;
   for (int e = threadIdx.x; e < Kh * Ky; e += blockDim.x) {
     const int k = e >> lky, y = e & (Ky - 1);
     out[(unsigned)imul(imul(k, Kz) + z, Ky) + y] = ty_tile[imul(k, RY) + lds_pad(y)];
@@ -1161,28 +1171,42 @@ __global__ void __launch_bounds__(1024) k_ifft_xy(const cpx<T>* __restrict__ fsp
   const int lkx = 31 - __clz(Kx), lky = 31 - __clz(Ky);
   copy_g2s<8>(tw, twg, g.twN);
 
-  // rows (kx, z) of component a: Ky contiguous values each, Kz * Ky apart
+  // rows (kx, z) of component a: Ky contiguous values each, Kz * Ky apart.
+  // The fused form loads them straight into the transform's registers.
   constexpr int kMax = 16;  // host: Kh * Ky <= 16 * blockDim.x
-  {
-    const cpx<T>* src = fspec + (size_t)a * Kh * Kz * Ky + (size_t)z * Ky;
-    const size_t rstride = (size_t)Kz * Ky;
+  const cpx<T>* src = fspec + (size_t)a * Kh * Kz * Ky + (size_t)z * Ky;
+  const size_t rstride = (size_t)Kz * Ky;
+  auto load_g = [&](int k, int y) { return src[(size_t)k * rstride + y]; };
+  auto store_ty = [&](int k, int y, const cpx<T>& v) { ty[imul(k, RY) + lds_pad(y)] = v; };
+  if (!fft_rows_io<T, true>(ty, Kh, Ky, RY, tw, g.twN, load_g, store_ty)) {
     cpx<T> r[kMax];
 #pragma unroll
     for (int c = 0; c < kMax; ++c) {
       const int e = threadIdx.x + c * blockDim.x;
-      if (e < Kh * Ky) r[c] = src[(size_t)(e >> lky) * rstride + (e & (Ky - 1))];
+      if (e < Kh * Ky) r[c] = load_g(e >> lky, e & (Ky - 1));
     }
 #pragma unroll
     for (int c = 0; c < kMax; ++c) {
       const int e = threadIdx.x + c * blockDim.x;
-      if (e < Kh * Ky) ty[imul(e >> lky, RY) + lds_pad(e & (Ky - 1))] = r[c];
+      if (e < Kh * Ky) store_ty(e >> lky, e & (Ky - 1), r[c]);
     }
+    __syncthreads();
+    fft_rows<T, true, kEPT, true>(ty, Kh, Ky, RY, 1, false, tw, g.twN);
   }
-  __syncthreads();
-  fft_rows<T, true, kEPT, true>(ty, Kh, Ky, RY, 1, false, tw, g.twN);
 
-  // [kx][y] -> complex row pairs along x, in place through registers
-  {
+  // complex row pairs along x: pair pr takes A + iB (A, B: rows 2pr, 2pr+1)
+  // for kx <= Kx/2 and conj(A) + i conj(B) at Kx - kx.  The fused form builds
+  // them on the way into the transform.
+  auto load_r = [&](int pr, int m) {
+    const bool up = m > Kx / 2;
+    const int k = up ? Kx - m : m;
+    const cpx<T>* row = ty + imul(k, RY);
+    cpx<T> av = row[lds_pad(2 * pr)], bv = row[lds_pad(2 * pr + 1)];
+    if (k == 0 || k == Kx / 2) { av.y = (T)0; bv.y = (T)0; }
+    return up ? cpx<T>{av.x + bv.y, bv.x - av.y} : cpx<T>{av.x - bv.y, av.y + bv.x};
+  };
+  auto store_tx = [&](int pr, int x, const cpx<T>& v) { tx[imul(pr, RS) + lds_pad(x)] = v; };
+  if (!fft_rows_io<T, true>(tx, Ky / 2, Kx, RS, tw, g.twN, load_r, store_tx)) {
     const int half = Ky >> 1, lhalf = lky - 1;
     constexpr int kPairs = kMax / 2;  // Kh * Ky / 2 <= 8 * blockDim.x
     cpx<T> A[kPairs], B[kPairs];
@@ -1209,11 +1233,12 @@ __global__ void __launch_bounds__(1024) k_ifft_xy(const cpx<T>* __restrict__ fsp
         if (k > 0 && k < Kx / 2) zr[lds_pad(Kx - k)] = cpx<T>{av.x + bv.y, bv.x - av.y};
       }
     }
+    __syncthreads();
+    fft_rows<T, true, kEPT, true>(tx, Ky / 2, Kx, RS, 1, false, tw, g.twN);
   }
-  __syncthreads();
-  fft_rows<T, true, kEPT, true>(tx, Ky / 2, Kx, RS, 1, false, tw, g.twN);
 
-  // real rows: y even in the real parts, y odd in the imaginary parts
+  // real rows (y even in the real parts, y odd in the imaginary parts) to
+  // component a of the field records, consecutive threads on consecutive x
   const T* tr = reinterpret_cast<const T*>(tx);
   T* out = field + (size_t)z * Ky * Kx * 3 + a;
   for (int e = threadIdx.x; e < Ky * Kx; e += blockDim.x) {
