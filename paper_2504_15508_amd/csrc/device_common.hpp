@@ -230,6 +230,29 @@ __device__ __forceinline__ void fft_rows_reg(cpx<T>* buf, int nrows, int rstride
       [&](int r, int e, const cpx<T>& x) { elem(r, e) = x; });
 }
 
+// Column transforms (element e of column c at buf[e * estride + c], consecutive
+// threads on consecutive columns) with fused input and output: applicable for
+// FP32 columns of N = 16 L <= 256 points when the block has ncols * L
+// threads; false (nothing done) otherwise.
+template <typename T, bool INV, typename LoadF, typename StoreF>
+__device__ __forceinline__ bool fft_cols_io(cpx<T>* buf, int ncols, int N, int estride, const cpx<T>* tw, int twN,
+                                            LoadF load, StoreF store) {
+  if constexpr (sizeof(T) != 4) {
+    return false;
+  } else {
+    const int L = N / 16;
+    if (N < 16 || N > 256 || ncols * L > (int)blockDim.x) return false;
+    switch (L) {
+      case 1: fft_rows_reg_io<T, 1, INV, false>(buf, ncols, 1, estride, true, tw, twN, load, store); return true;
+      case 2: fft_rows_reg_io<T, 2, INV, false>(buf, ncols, 1, estride, true, tw, twN, load, store); return true;
+      case 4: fft_rows_reg_io<T, 4, INV, false>(buf, ncols, 1, estride, true, tw, twN, load, store); return true;
+      case 8: fft_rows_reg_io<T, 8, INV, false>(buf, ncols, 1, estride, true, tw, twN, load, store); return true;
+      case 16: fft_rows_reg_io<T, 16, INV, false>(buf, ncols, 1, estride, true, tw, twN, load, store); return true;
+    }
+    return false;
+  }
+}
+
 // Row transforms (PAD layout, exchange through buf) with fused input and
 // output: applicable for FP32 rows of N = 16 L <= 256 points when the block
 // has nrows * L threads; false (nothing done) otherwise.

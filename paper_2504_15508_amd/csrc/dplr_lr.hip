@@ -39,6 +39,10 @@ thread_local std::string g_global_error;
 #define DPLR_SORT_CHUNKS 256
 #endif
 static_assert(DPLR_SORT_CHUNKS >= 1 && DPLR_SORT_CHUNKS <= 256, "sort chunk count out of range");
+// rows per sort bin in plane mode (log2): the gather walks the particles in bin order
+#ifndef DPLR_PLANE_QSHIFT
+#define DPLR_PLANE_QSHIFT 4
+#endif
 #ifndef DPLR_SORT_CHUNK_ALIGN
 #define DPLR_SORT_CHUNK_ALIGN 256
 #endif
@@ -227,7 +231,7 @@ bool choose_geometry(dplr_lr_plan p) {
       g.split_by_index = 1;
       // a plane visits all row groups of its planes: coarse groups keep the
       // sort small while consecutive particles stay close in y
-      g.qshift = std::min(4, 31 - __builtin_clz((unsigned)Ky));
+      g.qshift = std::min(DPLR_PLANE_QSHIFT, 31 - __builtin_clz((unsigned)Ky));
       g.NQ = Ky >> g.qshift;
       g.nbins = g.nsplit * Kz * g.NQ;
       g.scy = Ky; g.scz = 1; g.spy = 1; g.spz = Kz;

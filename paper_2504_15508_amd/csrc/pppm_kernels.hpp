@@ -961,31 +961,42 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
   const int kx = blk / nyb, y0 = (blk - kx * nyb) << lyb;
   const unsigned col0 = (unsigned)imul(imul(kx, Kz), Ky) + y0;  // spec[kx][0][y0]
   const int n = Kz << lyb;                                      // elements (z, yl), yl fastest
-  for (int base = threadIdx.x; base < n; base += 8 * blockDim.x) {
-    cpx<T> r[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = base + u * blockDim.x;
-      if (e < n) r[u] = spec[col0 + imul(e >> lyb, Ky) + (e & (yb - 1))];
-    }
-    // partial spectra of the other particle splits, added in split order
-    for (int sp = 1; sp < nsum; ++sp) {
-      const cpx<T>* ps = spec + (size_t)sp * sum_stride;
+  // forward z transform of the yb columns, the partial spectra of the particle
+  // splits added in split order on the way in
+  copy_g2s<8>(tw, twg, g.twN);
+  auto load_s = [&](int yl, int z) {
+    const unsigned o = col0 + imul(z, Ky) + yl;
+    cpx<T> v = spec[o];
+    for (int sp = 1; sp < nsum; ++sp) v = cadd(v, spec[(size_t)sp * sum_stride + o]);
+    return v;
+  };
+  auto store_b = [&](int yl, int z, const cpx<T>& v) { buf[imul(z, w3) + yl] = v; };
+  if (!fft_cols_io<T, false>(buf, yb, Kz, w3, tw, g.twN, load_s, store_b)) {
+    for (int base = threadIdx.x; base < n; base += 8 * blockDim.x) {
+      cpx<T> r[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = base + u * blockDim.x;
-        if (e < n) r[u] = cadd(r[u], ps[col0 + imul(e >> lyb, Ky) + (e & (yb - 1))]);
+        if (e < n) r[u] = spec[col0 + imul(e >> lyb, Ky) + (e & (yb - 1))];
+      }
+      // partial spectra of the other particle splits, added in split order
+      for (int sp = 1; sp < nsum; ++sp) {
+        const cpx<T>* ps = spec + (size_t)sp * sum_stride;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = base + u * blockDim.x;
+          if (e < n) r[u] = cadd(r[u], ps[col0 + imul(e >> lyb, Ky) + (e & (yb - 1))]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * blockDim.x;
+        if (e < n) buf[imul(e >> lyb, w3) + (e & (yb - 1))] = r[u];
       }
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = base + u * blockDim.x;
-      if (e < n) buf[imul(e >> lyb, w3) + (e & (yb - 1))] = r[u];
-    }
+    __syncthreads();
+    fft_rows<T, false, kEPT>(buf, yb, Kz, 1, w3, true, tw, g.twN);
   }
-  copy_g2s<8>(tw, twg, g.twN);
-  __syncthreads();
-  fft_rows<T, false, kEPT>(buf, yb, Kz, 1, w3, true, tw, g.twN);
 
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   const int Kyh = Ky / 2 + 1, Kzh = Kz / 2 + 1;
@@ -1034,13 +1045,21 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
     }
   }
   __syncthreads();
-  fft_rows<T, true, kEPT>(buf, w3, Kz, 1, w3, true, tw, g.twN);
-  // store: e = ((z * 3 + a) << lyb) + yl
+  // three inverse z transforms; the fused form writes the field spectra directly
   const unsigned fstride = (unsigned)imul(imul(Kh, Kz), Ky);
-  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
-    const int za = e >> lyb, yl = e & (yb - 1);
-    const int z = za / 3, a = za - 3 * z;
-    fspec[a * fstride + col0 + imul(z, Ky) + yl] = buf[imul(z, w3) + imul(a, yb) + yl];
+  auto store_f = [&](int c, int z, const cpx<T>& v) {
+    const int a = c >> lyb, yl = c & (yb - 1);  // column c = a * yb + yl
+    fspec[a * fstride + col0 + imul(z, Ky) + yl] = v;
+  };
+  auto load_b = [&](int c, int z) { return buf[imul(z, w3) + c]; };
+  if (!fft_cols_io<T, true>(buf, w3, Kz, w3, tw, g.twN, load_b, store_f)) {
+    fft_rows<T, true, kEPT>(buf, w3, Kz, 1, w3, true, tw, g.twN);
+    // store: e = ((z * 3 + a) << lyb) + yl
+    for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
+      const int za = e >> lyb, yl = e & (yb - 1);
+      const int z = za / 3, a = za - 3 * z;
+      fspec[a * fstride + col0 + imul(z, Ky) + yl] = buf[imul(z, w3) + imul(a, yb) + yl];
+    }
   }
 
   // deterministic block reduction of the 7 FP64 partial sums
