@@ -30,6 +30,15 @@ particle-mesh method in its order:
 With k = 2 pi m the factor phi/(2V) equals the paper's exp(-pi^2 m^2/beta^2) /
 (2 pi V m^2), so as h -> 0 this converges to the direct Ewald sum.
 Everything here uses full (not half) spectra and numpy.fft.
+
+pppm_ad() is the analytic-differentiation variant of the same energy (not in
+the paper, which uses ik; it is the adjacent textbook scheme).  Steps 1-5 and
+9 are shared; the forces are the exact gradient of the step-5 energy:
+ 6'. potential phi(g) = sum_n G(n) Q^(n) exp(+2 pi i n.g/K) (one inverse DFT);
+ 7'. since dE/dQ(g) = (k_e/V) phi(g) and dQ(g)/dr_ja = q_j dW/du_a / h_a,
+        F_ja = -(k_e q_j / (V h_a)) sum_g phi(g) M'_p(u_ja - g_a + p/2)
+                                        prod_{b != a} M_p(u_jb - g_b + p/2),
+     with the B-spline derivative M'_p(x) = M_{p-1}(x) - M_{p-1}(x - 1).
 """
 from __future__ import annotations
 
@@ -56,6 +65,12 @@ def stencil(u, p: int):
     g = s[:, None] + np.arange(p)[None, :]
     w = bspline(p, u[:, None] - g + p / 2.0)
     return g, w
+
+
+def dbspline(p: int, x):
+    """Derivative of the cardinal B-spline: M'_p(x) = M_{p-1}(x) - M_{p-1}(x - 1)."""
+    x = np.asarray(x, dtype=np.float64)
+    return bspline(p - 1, x) - bspline(p - 1, x - 1.0)
 
 
 def mesh_coords(pos, box, K):
@@ -104,6 +119,29 @@ def interpolate(pos, box, K, p: int, field):
             for tz in range(p):
                 gz = np.mod(st[2][0][:, tz], K[2])
                 out += wxy * st[2][1][:, tz] * flat[(gx * K[1] + gy) * K[2] + gz]
+    return out
+
+
+def interpolate_grad(pos, box, K, p: int, field):
+    """[n, 3]: sum_g field(g) dW(u_j - g)/du_a for a = x, y, z, where
+    W(d) = prod_b M_p(d_b + p/2) is the assignment function of spread()."""
+    K = tuple(int(k) for k in K)
+    u = mesh_coords(pos, box, K)
+    st = [stencil(u[:, a], p) for a in range(3)]
+    dw = [dbspline(p, u[:, a][:, None] - st[a][0] + p / 2.0) for a in range(3)]
+    out = np.zeros((u.shape[0], 3))
+    flat = field.reshape(-1)
+    for tx in range(p):
+        gx = np.mod(st[0][0][:, tx], K[0])
+        for ty in range(p):
+            gy = np.mod(st[1][0][:, ty], K[1])
+            for tz in range(p):
+                gz = np.mod(st[2][0][:, tz], K[2])
+                f = flat[(gx * K[1] + gy) * K[2] + gz]
+                wx, wy, wz = st[0][1][:, tx], st[1][1][:, ty], st[2][1][:, tz]
+                out[:, 0] += f * dw[0][:, tx] * wy * wz
+                out[:, 1] += f * wx * dw[1][:, ty] * wz
+                out[:, 2] += f * wx * wy * dw[2][:, tz]
     return out
 
 
@@ -180,6 +218,38 @@ def pppm(pos, q, box, K, p: int, beta: float, ke: float, alias: int = 2, G=None,
         F[:, a] = ke * q / V * interpolate(pos, box, K, p, Ea.real)
     if return_parts:
         return E, F, W, dict(Q=Q, Qhat=Qh, G=G, fields=fields)
+    return E, F, W
+
+
+def pppm_ad(pos, q, box, K, p: int, beta: float, ke: float, alias: int = 2, G=None,
+            return_parts: bool = False):
+    """PPPM energy and virial as pppm(), with forces by analytic
+    differentiation of the assignment weights: F = -dE/dr of the returned E."""
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    q = np.asarray(q, dtype=np.float64).reshape(-1)
+    box = np.asarray(box, dtype=np.float64).reshape(3)
+    K = [int(k) for k in K]
+    V = float(np.prod(box))
+    h = box / np.asarray(K)
+    Q = spread(pos, q, box, K, p)
+    Qh = np.fft.fftn(Q)
+    if G is None:
+        G = influence(box, K, beta, p, alias)
+    n, k = wavevectors(box, K)
+    kg = np.meshgrid(k[0], k[1], k[2], indexing="ij")
+    s2 = (Qh.conj() * Qh).real
+    E = ke / (2 * V) * float((G * s2).sum())
+    k2 = kg[0] ** 2 + kg[1] ** 2 + kg[2] ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        c = np.where(k2 > 0, 2 * (1 + k2 / (4 * beta * beta)) / k2, 0.0)
+    W = np.empty(6)
+    for i, (a, b) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        W[i] = ke / (2 * V) * float((G * s2 * ((1.0 if a == b else 0.0) - c * kg[a] * kg[b])).sum())
+    ntot = K[0] * K[1] * K[2]
+    phi = (np.fft.ifftn(G * Qh) * ntot).real
+    F = -(ke / V) * q[:, None] * interpolate_grad(pos, box, K, p, phi) / h[None, :]
+    if return_parts:
+        return E, F, W, dict(Q=Q, Qhat=Qh, G=G, phi=phi)
     return E, F, W
 
 

@@ -157,3 +157,40 @@ def test_real_fields(w64):
         Eh = -1j * kd.reshape(shape) * parts["G"] * parts["Qhat"]
         Ea = np.fft.ifftn(Eh) * 16 ** 3
         assert np.abs(Ea.imag).max() < 1e-12 * np.abs(Ea.real).max()
+
+
+# ---------------------------------------------------------------------------
+# Analytic-differentiation variant: its forces are the exact gradient of the
+# PPPM energy, so central finite differences of pppm()'s energy pin every
+# step of it (spread, transforms, influence function, derivative weights,
+# normalisation and sign).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("p", [2, 3, 5, 8])
+def test_bspline_derivative_matches_finite_differences(p):
+    x = np.linspace(0.013, p - 0.017, 97)
+    h = 1e-6
+    fd = (pppm.bspline(p, x + h) - pppm.bspline(p, x - h)) / (2 * h)
+    assert np.abs(pppm.dbspline(p, x) - fd).max() < 1e-8
+
+
+@pytest.mark.parametrize("p", [3, 5, 8])
+def test_ad_forces_are_the_energy_gradient(p):
+    s = systems.workload(1).system()
+    pos, q, box = s.all_pos(), s.all_q(), s.box
+    K = (16, 16, 16)
+    G = pppm.influence(box, K, BETA, p)
+    E, F, W = pppm.pppm_ad(pos, q, box, K, p, BETA, KE, G=G)
+    E_ik = pppm.pppm(pos, q, box, K, p, BETA, KE, G=G)[0]
+    assert abs(E - E_ik) <= 1e-14 * abs(E)
+    step = 1e-5
+    for j in (0, 7, 100, s.n - 1):
+        for a in range(3):
+            d = []
+            for sg in (1, -1):
+                r = pos.copy()
+                r[j, a] += sg * step
+                d.append(pppm.pppm_ad(r, q, box, K, p, BETA, KE, G=G)[0])
+            fd = -(d[0] - d[1]) / (2 * step)
+            # measured ~1e-9 (FD truncation and rounding); the ik forces of the
+            # same energy differ by 3e-4 (p = 5) to 6e-6 (p = 8)
+            assert abs(F[j, a] - fd) <= 1e-8 * np.abs(F[j]).max()
