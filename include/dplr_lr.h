@@ -65,6 +65,16 @@ typedef enum { DPLR_LR_FP32 = 0, DPLR_LR_FP64 = 1 } dplr_lr_precision;
 /* flags */
 #define DPLR_LR_ACCUMULATE 0x1u   /* add forces into the output arrays instead of overwriting */
 #define DPLR_LR_NO_VIRIAL  0x2u   /* skip the virial reduction (virial6 may be NULL)         */
+/* Forces by analytic differentiation of the B-spline assignment weights
+ * instead of ik: the potential phi(g) = sum_n G(n) Q^(n) exp(2 pi i n.g/K)
+ * takes one inverse FFT (instead of three), and
+ *   F_ja = -(k_e q_j / (V h_a)) sum_g phi(g) dW(u_j - g)/du_a
+ * is the exact gradient of the returned energy (same E and virial as ik).
+ * Not the paper's choice (it uses Poisson-IK); the adjacent textbook
+ * variant.  The net force is not exactly zero.  Needs z planes that fit in
+ * LDS (Kx * Ky <= 16384 at FP32); otherwise plan creation returns
+ * DPLR_LR_E_UNSUPPORTED. */
+#define DPLR_LR_DIFF_AD    0x4u
 
 typedef struct {
   int32_t mesh[3];     /* Kx, Ky, Kz: powers of two in [16, 512]                          */
@@ -75,7 +85,7 @@ typedef struct {
                           table and the energy/virial reductions are FP64 in both modes  */
   int32_t alias_range; /* |m_a| <= alias_range in the influence-function alias sums, 0..4 */
   int64_t capacity;    /* maximum n_ion + n_wc per call, 0 .. 2^31 - 1                    */
-  uint32_t flags;      /* DPLR_LR_ACCUMULATE | DPLR_LR_NO_VIRIAL                          */
+  uint32_t flags;      /* DPLR_LR_ACCUMULATE | DPLR_LR_NO_VIRIAL | DPLR_LR_DIFF_AD        */
 } dplr_lr_config;
 
 /* Version of this ABI (DPLR_LR_ABI_VERSION of the built library). */

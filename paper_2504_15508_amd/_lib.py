@@ -14,7 +14,7 @@ OK, E_INVALID, E_UNSUPPORTED, E_NO_BOX, E_CAPACITY, E_DEVICE, E_NOMEM = range(7)
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_UNSUPPORTED", 3: "E_NO_BOX", 4: "E_CAPACITY",
                 5: "E_DEVICE", 6: "E_NOMEM"}
 FP32, FP64 = 0, 1
-ACCUMULATE, NO_VIRIAL = 0x1, 0x2
+ACCUMULATE, NO_VIRIAL, DIFF_AD = 0x1, 0x2, 0x4
 BUF_SPECTRUM, BUF_INFLUENCE, BUF_FIELD_SPECTRA = 0, 1, 2
 
 # every symbol include/dplr_lr.h declares

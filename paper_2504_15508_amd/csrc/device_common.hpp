@@ -459,4 +459,42 @@ __device__ __forceinline__ void bspline_weights(T d, T* w) {
   }
 }
 
+// Derivatives dw[t] = M'_P(d + P-1-t) of the weights above with respect to the
+// mesh coordinate (the derivative of each polynomial, also by Horner).
+template <typename T, int P>
+__device__ __forceinline__ void bspline_dweights(T d, T* dw) {
+  constexpr BsplineCoeffs<P> C{};
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    const int i = P - 1 - t;
+    T v = (T)((P - 1) * C.c[i][P - 1]);
+#pragma unroll
+    for (int j = P - 2; j >= 1; --j) v = v * d + (T)(j * C.c[i][j]);
+    dw[t] = v;
+  }
+}
+
+// Weight w[t] and derivative dw[t] of one stencil point t (runtime, 0..P-1):
+// the polynomial's coefficients are selected first, then evaluated by Horner.
+template <typename T, int P>
+__device__ __forceinline__ void bspline_weight_at(T d, int t, T& w, T& dw) {
+  constexpr BsplineCoeffs<P> C{};
+  T c[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    T v = (T)C.c[P - 1][j];
+#pragma unroll
+    for (int k = 1; k < P; ++k) v = (t == k) ? (T)C.c[P - 1 - k][j] : v;
+    c[j] = v;
+  }
+  T a = c[P - 1], b = (T)(P - 1) * c[P - 1];
+#pragma unroll
+  for (int j = P - 2; j >= 0; --j) {
+    a = a * d + c[j];
+    if (j >= 1) b = b * d + (T)j * c[j];
+  }
+  w = a;
+  dw = b;
+}
+
 }  // namespace dplr

@@ -57,6 +57,9 @@ static_assert(DPLR_SORT_CHUNKS >= 1 && DPLR_SORT_CHUNKS <= 256, "sort chunk coun
 #ifndef DPLR_IXY_MIN_THREADS
 #define DPLR_IXY_MIN_THREADS 64
 #endif
+#ifndef DPLR_IXY_AD_THREADS
+#define DPLR_IXY_AD_THREADS 64
+#endif
 #ifndef DPLR_FFTZ_COLS
 #define DPLR_FFTZ_COLS 8
 #endif
@@ -94,7 +97,10 @@ dplr_lr_status validate(const dplr_lr_config* c, std::string& msg) {
   if (c->precision != DPLR_LR_FP32 && c->precision != DPLR_LR_FP64) { msg = "precision must be FP32 or FP64"; return DPLR_LR_E_INVALID; }
   if (c->alias_range < 0 || c->alias_range > 4) { msg = "alias_range must be in [0, 4]"; return DPLR_LR_E_INVALID; }
   if (c->capacity < 0 || c->capacity > 0x7fffffffLL) { msg = "capacity must be in [0, 2^31-1]"; return DPLR_LR_E_INVALID; }
-  if (c->flags & ~(uint32_t)(DPLR_LR_ACCUMULATE | DPLR_LR_NO_VIRIAL)) { msg = "unknown flag bits"; return DPLR_LR_E_INVALID; }
+  if (c->flags & ~(uint32_t)(DPLR_LR_ACCUMULATE | DPLR_LR_NO_VIRIAL | DPLR_LR_DIFF_AD)) {
+    msg = "unknown flag bits";
+    return DPLR_LR_E_INVALID;
+  }
   return DPLR_LR_OK;
 }
 
@@ -305,7 +311,9 @@ bool choose_geometry(dplr_lr_plan p) {
   p->ixy = false;
   if (p->plane && Kz % 8 == 0) {
     const long e_y = (long)g.Kh * Ky, e_x = (long)(Ky / 2) * Kx;
-    const int thr = std::max(DPLR_IXY_MIN_THREADS, (int)(((std::max(e_y, e_x) + kEPT - 1) / kEPT + 63) / 64 * 64));
+    // analytic differentiation has one component per plane (Kz blocks): more threads per block
+    const int thr_min = (p->cfg.flags & DPLR_LR_DIFF_AD) ? DPLR_IXY_AD_THREADS : DPLR_IXY_MIN_THREADS;
+    const int thr = std::max(thr_min, (int)(((std::max(e_y, e_x) + kEPT - 1) / kEPT + 63) / 64 * 64));
     const size_t b_y = (size_t)g.Kh * (padded_len(Ky) + 1) * cs, b_x = (size_t)(Ky / 2) * (padded_len(Kx) + 1) * cs;
     const size_t lds = std::max(std::max(b_y, b_x) + twb, (size_t)7 * thr * sizeof(double));
     if (thr <= 1024 && lds <= budget) {
@@ -460,18 +468,21 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
   PoissonConsts pc;
   for (int a = 0; a < 3; ++a) pc.two_pi_over_L[a] = 2.0 * M_PI / p->box[a];
   pc.inv_4beta2 = 1.0 / (4.0 * p->cfg.beta * p->cfg.beta);
+  // field components: three (ik) or the potential alone (analytic differentiation)
+  const bool ad = (p->cfg.flags & DPLR_LR_DIFF_AD) != 0;
+  const int ncomp = ad ? 1 : 3;
   {
     ProfScope ps(p, 5);
     hipLaunchKernelGGL((k_fftz_poisson<T>), dim3((g.nzblk + 8 * g.zgroup - 1) / (8 * g.zgroup) * 8 * g.zgroup),
                        dim3(p->thr_z), p->lds_z, s, spec,
-                       p->plane ? g.nsplit : 1, nspec, fspec, p->G, p->partials, tw, g, pc);
+                       p->plane ? g.nsplit : 1, nspec, ncomp, fspec, p->G, p->partials, tw, g, pc);
   }
   const double V = p->box[0] * p->box[1] * p->box[2];
   const bool want_virial = !(p->cfg.flags & DPLR_LR_NO_VIRIAL) && virial;
   if (p->ixy) {
     ProfScope ps(p, 10);
-    hipLaunchKernelGGL((k_ifft_xy<T>), dim3(3 * g.K[2]), dim3(p->thr_ixy), p->lds_ixy, s, fspec,
-                       reinterpret_cast<T*>(p->field), tw, g, (const double*)p->partials,
+    hipLaunchKernelGGL((k_ifft_xy<T>), dim3(ncomp * g.K[2]), dim3(p->thr_ixy), p->lds_ixy, s, fspec,
+                       reinterpret_cast<T*>(p->field), ncomp, tw, g, (const double*)p->partials,
                        p->cfg.coulomb_k / (2.0 * V), energy, want_virial ? virial : (double*)nullptr);
   } else {
     ProfScope ps(p, 6);
@@ -491,9 +502,17 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
       const int per_block = 4 * (64 / P);
       const int nchunks = (int)((n + per_block - 1) / per_block);
       const int nblk = (nchunks + kXcd - 1) / kXcd * kXcd;
-      hipLaunchKernelGGL((k_gather<T, P>), dim3(nblk), dim3(256), 0, s, reinterpret_cast<const F3<T>*>(p->field),
-                         sorted, p->sidx, p->perm, (int)n, nchunks, (T*)ion_force, (T*)wc_force, n_ion,
-                         (T)(p->cfg.coulomb_k / V), (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0, kXcd, g);
+      const int acc = (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0;
+      if (ad) {
+        hipLaunchKernelGGL((k_gather_ad<T, P>), dim3(nblk), dim3(256), 0, s, reinterpret_cast<const T*>(p->field),
+                           sorted, p->sidx, p->perm, (int)n, nchunks, (T*)ion_force, (T*)wc_force, n_ion,
+                           (T)(p->cfg.coulomb_k / V), (T)(g.K[0] / p->box[0]), (T)(g.K[1] / p->box[1]),
+                           (T)(g.K[2] / p->box[2]), acc, kXcd, g);
+      } else {
+        hipLaunchKernelGGL((k_gather<T, P>), dim3(nblk), dim3(256), 0, s, reinterpret_cast<const F3<T>*>(p->field),
+                           sorted, p->sidx, p->perm, (int)n, nchunks, (T*)ion_force, (T*)wc_force, n_ion,
+                           (T)(p->cfg.coulomb_k / V), acc, kXcd, g);
+      }
     }
   }
   hipError_t e = hipGetLastError();
@@ -568,6 +587,11 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
   if (!choose_geometry(p)) {
     delete p;
     return fail(nullptr, DPLR_LR_E_UNSUPPORTED, "no tiling fits the device's LDS for this mesh/order/precision");
+  }
+  if ((cfg->flags & DPLR_LR_DIFF_AD) && !p->ixy) {
+    delete p;
+    return fail(nullptr, DPLR_LR_E_UNSUPPORTED,
+                "analytic differentiation needs z planes that fit in LDS (Kx * Ky <= 16384 here)");
   }
   const Geo& g = p->geo;
   const size_t ts = p->tsize, cs = 2 * ts;

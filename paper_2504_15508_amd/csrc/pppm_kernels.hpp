@@ -938,7 +938,7 @@ __global__ void __launch_bounds__(kFftyThreads) k_ffty(cpx<T>* __restrict__ data
 // ----------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict__ spec, int nsum, size_t sum_stride,
-                                                       cpx<T>* __restrict__ fspec,
+                                                       int ncomp, cpx<T>* __restrict__ fspec,
                                                        const double* __restrict__ G, double* __restrict__ partials,
                                                        const cpx<T>* __restrict__ twg, Geo g, PoissonConsts pc) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1037,27 +1037,34 @@ __global__ void __launch_bounds__(1024) k_fftz_poisson(const cpx<T>* __restrict_
       acc[4] += t * (-c * kxd * kyd);
       acc[5] += t * (-c * kxd * kzd);
       acc[6] += t * (-c * kyd * kzd);
-      // -i k' G Q^ = k' G (q.y, -q.x)
-      const T gx = (T)(Gv * kxd), gy = (T)(Gv * kyd), gz = (T)(Gv * kzd);
-      bz[0] = cpx<T>{gx * q.y, -gx * q.x};
-      bz[yb] = cpx<T>{gy * q.y, -gy * q.x};
-      bz[2 * yb] = cpx<T>{gz * q.y, -gz * q.x};
+      if (ncomp == 1) {
+        // analytic differentiation: the potential spectrum G Q^
+        const T gv = (T)Gv;
+        bz[0] = cpx<T>{gv * q.x, gv * q.y};
+      } else {
+        // -i k' G Q^ = k' G (q.y, -q.x)
+        const T gx = (T)(Gv * kxd), gy = (T)(Gv * kyd), gz = (T)(Gv * kzd);
+        bz[0] = cpx<T>{gx * q.y, -gx * q.x};
+        bz[yb] = cpx<T>{gy * q.y, -gy * q.x};
+        bz[2 * yb] = cpx<T>{gz * q.y, -gz * q.x};
+      }
     }
   }
   __syncthreads();
-  // three inverse z transforms; the fused form writes the field spectra directly
+  // ncomp inverse z transforms (three field components, or the potential);
+  // the fused form writes the spectra directly
   const unsigned fstride = (unsigned)imul(imul(Kh, Kz), Ky);
   auto store_f = [&](int c, int z, const cpx<T>& v) {
     const int a = c >> lyb, yl = c & (yb - 1);  // column c = a * yb + yl
     fspec[a * fstride + col0 + imul(z, Ky) + yl] = v;
   };
   auto load_b = [&](int c, int z) { return buf[imul(z, w3) + c]; };
-  if (!fft_cols_io<T, true>(buf, w3, Kz, w3, tw, g.twN, load_b, store_f)) {
-    fft_rows<T, true, kEPT>(buf, w3, Kz, 1, w3, true, tw, g.twN);
-    // store: e = ((z * 3 + a) << lyb) + yl
-    for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
+  if (!fft_cols_io<T, true>(buf, ncomp * yb, Kz, w3, tw, g.twN, load_b, store_f)) {
+    fft_rows<T, true, kEPT>(buf, ncomp * yb, Kz, 1, w3, true, tw, g.twN);
+    // store: e = ((z * ncomp + a) << lyb) + yl
+    for (int e = threadIdx.x; e < ncomp * n; e += blockDim.x) {
       const int za = e >> lyb, yl = e & (yb - 1);
-      const int z = za / 3, a = za - 3 * z;
+      const int z = za / ncomp, a = za - ncomp * z;
       fspec[a * fstride + col0 + imul(z, Ky) + yl] = buf[imul(z, w3) + imul(a, yb) + yl];
     }
   }
@@ -1164,15 +1171,16 @@ __global__ void __launch_bounds__(512) k_ifftx(const cpx<T>* __restrict__ fspec,
 // A + iB for kx <= Kx/2 and conj(A) + i conj(B) at Kx - kx (Hermitian
 // symmetry), with the imaginary parts of the kx = 0 and Kx/2 terms dropped.
 // One inverse complex FFT per pair along x gives both real rows, written as
-// component a of the interleaved field records.  Block b serves plane
-// z = 8 (b / 24) + b % 8 and component (b / 8) % 3, so the three components of a
-// plane land on the same XCD (blocks are dealt round-robin over 8 XCDs) and
-// its L2 merges their partial record writes.  Block 0 also performs the final
-// energy/virial reduction.
+// component a of the interleaved field records (ncomp = 3 field components
+// for ik differentiation, ncomp = 1 for the potential of analytic
+// differentiation).  Block b serves plane z = 8 (b / (8 ncomp)) + b % 8 and
+// component (b / 8) % ncomp, so the components of a plane land on the same XCD
+// (blocks are dealt round-robin over 8 XCDs) and its L2 merges their partial
+// record writes.  Block 0 also performs the final energy/virial reduction.
 // ----------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(1024) k_ifft_xy(const cpx<T>* __restrict__ fspec, T* __restrict__ field,
-                                                  const cpx<T>* __restrict__ twg, Geo g,
+                                                  int ncomp, const cpx<T>* __restrict__ twg, Geo g,
                                                   const double* __restrict__ partials, double pre,
                                                   double* __restrict__ energy, double* __restrict__ virial) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1185,7 +1193,7 @@ __global__ void __launch_bounds__(1024) k_ifft_xy(const cpx<T>* __restrict__ fsp
   const size_t b_tx = (size_t)(Ky / 2) * RS * sizeof(cpx<T>);
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem + max(b_ty, b_tx));
   const int zx = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int zg = slot / 3, a = slot - 3 * zg;
+  const int zg = slot / ncomp, a = slot - ncomp * zg;
   const int z = zg * 8 + zx;
   const int lkx = 31 - __clz(Kx), lky = 31 - __clz(Ky);
   copy_g2s<8>(tw, twg, g.twN);
@@ -1257,12 +1265,13 @@ __global__ void __launch_bounds__(1024) k_ifft_xy(const cpx<T>* __restrict__ fsp
   }
 
   // real rows (y even in the real parts, y odd in the imaginary parts) to
-  // component a of the field records, consecutive threads on consecutive x
+  // component a of the field records (ncomp values per mesh point),
+  // consecutive threads on consecutive x
   const T* tr = reinterpret_cast<const T*>(tx);
-  T* out = field + (size_t)z * Ky * Kx * 3 + a;
+  T* out = field + (size_t)z * Ky * Kx * ncomp + a;
   for (int e = threadIdx.x; e < Ky * Kx; e += blockDim.x) {
     const int y = e >> lkx, x = e & (Kx - 1);
-    out[(size_t)e * 3] = tr[2 * (imul(y >> 1, RS) + lds_pad(x)) + (y & 1)];
+    out[(size_t)e * ncomp] = tr[2 * (imul(y >> 1, RS) + lds_pad(x)) + (y & 1)];
   }
   if (energy && blockIdx.x == 0) {
     __syncthreads();
@@ -1305,13 +1314,10 @@ __global__ void __launch_bounds__(256) DPLR_GATHER_OCC k_gather(const F3<T>* __r
     const int sp = sidx[v];
     src = perm[v];
     const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
-    T wx[P], wy[P], wz[P];
-    bspline_weights<T, P>(pt.x, wx);
+    T wy[P], wz[P], wxt, dxt;
+    bspline_weight_at<T, P>(pt.x, tx, wxt, dxt);  // this lane's column only
     bspline_weights<T, P>(pt.y, wy);
     bspline_weights<T, P>(pt.z, wz);
-    T wxt = wx[0];
-#pragma unroll
-    for (int q = 1; q < P; ++q) wxt = (tx == q) ? wx[q] : wxt;
     int gx = sx + tx;
     if (gx >= Kx) gx -= Kx;
     // all loads of a batch of z planes are issued before any of them is used
@@ -1357,6 +1363,101 @@ __global__ void __launch_bounds__(256) DPLR_GATHER_OCC k_gather(const F3<T>* __r
     T s = (T)0;
 #pragma unroll
     for (int q = 0; q < P; ++q) s += __shfl(mine, gbase + q, 64);
+    tot[a] = s;
+  }
+  if (on && tx == 0) {
+    T* out = (src < n_ion) ? (ion_f + 3 * (int64_t)src) : (wc_f + 3 * ((int64_t)src - n_ion));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a] = accumulate ? out[a] + tot[a] : tot[a];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Forces by analytic differentiation: F_ja = -(k_e q_j / (V h_a)) times
+// sum_g phi(g) dW(u_j - g)/du_a, with the potential phi read as one value per
+// mesh point.  P lanes serve one particle as in k_gather (lane tx reads the
+// column s_x + tx of all P x P (y, z) rows) and keep three partial sums:
+// phi wy wz (for the x derivative), phi wy' wz and phi wy wz' (for y and z),
+// which the lane then weights by wx' or wx before the sums over the group.
+// ----------------------------------------------------------------------------
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_gather_ad(const T* __restrict__ phi, const T4<T>* __restrict__ sorted,
+                                                   const int* __restrict__ sidx, const int* __restrict__ perm,
+                                                   int n, int nchunks, T* __restrict__ ion_f, T* __restrict__ wc_f,
+                                                   int64_t n_ion, T fscale, T ihx, T ihy, T ihz, int accumulate,
+                                                   int nxcd, Geo g) {
+  const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2];
+  constexpr int GPW = 64 / P;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / P, tx = lane - grp * P;
+  const bool lane_on = grp < GPW;
+  const int per_block = (blockDim.x >> 6) * GPW;
+  const int per_xcd = gridDim.x / nxcd;
+  const int chunk = (blockIdx.x % nxcd) * per_xcd + blockIdx.x / nxcd;
+  const int v = chunk * per_block + wave * GPW + grp;
+  const bool on = lane_on && chunk < nchunks && v < n;
+  T mine[3] = {(T)0, (T)0, (T)0};
+  int src = 0;
+  if (on) {
+    const T4<T> pt = sorted[v];
+    const int sp = sidx[v];
+    src = perm[v];
+    const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
+    T wy[P], wz[P], dy[P], dz[P], wxt, dxt;
+    bspline_weight_at<T, P>(pt.x, tx, wxt, dxt);  // this lane's column only
+    bspline_weights<T, P>(pt.y, wy);
+    bspline_weights<T, P>(pt.z, wz);
+    bspline_dweights<T, P>(pt.y, dy);
+    bspline_dweights<T, P>(pt.z, dz);
+    int gx = sx + tx;
+    if (gx >= Kx) gx -= Kx;
+    T s0 = (T)0, s1 = (T)0, s2 = (T)0;
+    constexpr int TZB = (P <= 5) ? P : ((P <= 6) ? 3 : 2);
+#pragma unroll
+    for (int tz0 = 0; tz0 < P; tz0 += TZB) {
+      T r[TZB][P];
+#pragma unroll
+      for (int d = 0; d < TZB; ++d) {
+        if (tz0 + d < P) {
+          int gz = sz + tz0 + d;
+          if (gz >= Kz) gz -= Kz;
+          const T* fz = phi + (unsigned)imul(gz, Ky) * (unsigned)Kx + gx;
+#pragma unroll
+          for (int ty = 0; ty < P; ++ty) {
+            int gy = sy + ty;
+            if (gy >= Ky) gy -= Ky;
+            r[d][ty] = fz[imul(gy, Kx)];
+          }
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < TZB; ++d) {
+        if (tz0 + d < P) {
+          const int tz = tz0 + d;
+          T a0 = (T)0, a1 = (T)0;
+#pragma unroll
+          for (int ty = 0; ty < P; ++ty) {
+            a0 += wy[ty] * r[d][ty];
+            a1 += dy[ty] * r[d][ty];
+          }
+          s0 += wz[tz] * a0;
+          s1 += wz[tz] * a1;
+          s2 += dz[tz] * a0;
+        }
+      }
+    }
+    const T qs = -fscale * pt.w;
+    mine[0] = qs * ihx * dxt * s0;
+    mine[1] = qs * ihy * wxt * s1;
+    mine[2] = qs * ihz * wxt * s2;
+  }
+  const int gbase = grp * P;
+  T tot[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    T s = (T)0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) s += __shfl(mine[a], gbase + k, 64);
     tot[a] = s;
   }
   if (on && tx == 0) {

@@ -20,15 +20,23 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 class Plan:
-    """A configured PPPM-ik plan (mesh, order, beta, precision, capacity).
+    """A configured PPPM plan (mesh, order, beta, precision, capacity).
 
+    diff selects the force scheme: "ik" (the paper's Poisson-IK, three
+    inverse FFTs) or "ad" (analytic differentiation of the assignment
+    weights, one inverse FFT; forces are the exact gradient of the energy).
     compute() returns (energy [0-d float64], ion_force [n_ion,3], wc_force
     [n_wc,3], virial [6] float64) as device tensors; forces are -dE/dr."""
 
     def __init__(self, mesh, order: int = 5, beta: float = 0.4, coulomb_k: float = 14.399645,
                  precision: str = "fp32", alias_range: int = 2, capacity: int = 0, flags: int = 0,
-                 device: Optional[torch.device] = None):
+                 device: Optional[torch.device] = None, diff: str = "ik"):
         lib = _lib.load()
+        if diff not in ("ik", "ad"):
+            raise ValueError("diff must be 'ik' or 'ad'")
+        if diff == "ad":
+            flags = int(flags) | _lib.DIFF_AD
+        self.diff = diff
         if isinstance(mesh, int):
             mesh = (mesh, mesh, mesh)
         if precision not in _DT:
