@@ -46,8 +46,9 @@ def _ref(pos, q, box, mesh=32, order=5):
                      (mesh,) * 3, order, BETA, KE)
 
 
-def test_empty_input(torch, dl):
-    p = _plan(dl)
+@pytest.mark.parametrize("diff", ["ik", "ad"])
+def test_empty_input(torch, dl, diff):
+    p = _plan(dl, flags=dl._lib.DIFF_AD if diff == "ad" else 0)
     E, fi, fw, W = p.compute(None, None, None, None)
     torch.cuda.synchronize()
     assert float(E) == 0.0 and np.all(W.cpu().numpy() == 0.0)
@@ -102,13 +103,15 @@ def test_coordinates_outside_box_are_wrapped(torch, dl):
     assert np.linalg.norm(F - F0) <= 1e-10 * np.linalg.norm(F0)
 
 
-def test_accumulate_and_no_virial_flags(torch, dl):
+@pytest.mark.parametrize("diff", ["ik", "ad"])
+def test_accumulate_and_no_virial_flags(torch, dl, diff):
     s = systems.workload(1).system()
     dt = torch.float64
     args = [_t(torch, s.ion_pos, dt), _t(torch, s.ion_q, dt), _t(torch, s.wc_pos, dt), _t(torch, s.wc_q, dt)]
-    p0 = _plan(dl)
+    extra = dl._lib.DIFF_AD if diff == "ad" else 0
+    p0 = _plan(dl, flags=extra)
     E0, fi0, fw0, W0 = p0.compute(*args)
-    p1 = _plan(dl, flags=dl._lib.ACCUMULATE | dl._lib.NO_VIRIAL)
+    p1 = _plan(dl, flags=dl._lib.ACCUMULATE | dl._lib.NO_VIRIAL | extra)
     fi = torch.ones_like(fi0)
     fw = torch.full_like(fw0, 2.0)
     vir = torch.full((6,), 7.0, dtype=torch.float64, device="cuda")
