@@ -53,7 +53,7 @@ typedef struct dplr_lr_plan_s* dplr_lr_plan;
 typedef enum {
   DPLR_LR_OK = 0,
   DPLR_LR_E_INVALID = 1,      /* bad argument (null pointer, negative size, ...) */
-  DPLR_LR_E_UNSUPPORTED = 2,  /* valid request outside what this build supports  */
+  DPLR_LR_E_UNSUPPORTED = 2,  /* valid request outside what the library supports */
   DPLR_LR_E_NO_BOX = 3,       /* compute before set_box                          */
   DPLR_LR_E_CAPACITY = 4,     /* more particles than the plan's capacity         */
   DPLR_LR_E_DEVICE = 5,       /* a HIP runtime call failed                       */

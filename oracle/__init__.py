@@ -1,4 +1,4 @@
-"""Reference implementations used to judge the GPU path.
+"""Reference implementations used to check the GPU path.
 
 TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the CPU
 baseline leg of bench.py may import anything here; the product package never

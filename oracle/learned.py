@@ -12,7 +12,7 @@ net producing atomic descriptors D_i from the neighbour list, then a
 three-layer fitting net); the Deep Wannier model predicts a vector per atom,
 which is the form used here for the force correction.
 
-Definitions (the reading this build takes; the paper gives no formulas):
+Definitions (the reading taken here; the paper gives no formulas):
   neighbours:  j != i with r_ij = |r_j - r_i| < r_c (minimum image), r_c = 4 A;
   radial basis g_k(r) = T_k(2 r / r_c - 1), Chebyshev of the first kind,
                k = 0..31, with the switch s(r) = (1 + cos(pi r / r_c)) / 2;
