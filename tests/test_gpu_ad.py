@@ -32,7 +32,8 @@ def torch_dev():
 def run(torch, sys, mesh, order, precision, diff="ad", flags=0):
     import paper_2504_15508_amd as dl
     dt = torch.float64 if precision == "fp64" else torch.float32
-    plan = dl.Plan((mesh,) * 3, order=order, beta=BETA, coulomb_k=KE, precision=precision,
+    mesh = (mesh,) * 3 if isinstance(mesh, int) else tuple(mesh)
+    plan = dl.Plan(mesh, order=order, beta=BETA, coulomb_k=KE, precision=precision,
                    capacity=sys.n, flags=flags, diff=diff)
     plan.set_box(sys.box)
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
@@ -51,7 +52,8 @@ def rel(a, b):
 def check(torch, sys, mesh, order, precision, tol_f, tol_e):
     E, F, W = run(torch, sys, mesh, order, precision)
     ref = sys.rounded(np.float32) if precision == "fp32" else sys
-    E0, F0, W0 = pppm.pppm_ad(ref.all_pos(), ref.all_q(), ref.box, (mesh,) * 3, order, BETA, KE)
+    K = (mesh,) * 3 if isinstance(mesh, int) else tuple(mesh)
+    E0, F0, W0 = pppm.pppm_ad(ref.all_pos(), ref.all_q(), ref.box, K, order, BETA, KE)
     dE, dF, dW = abs(E - E0) / abs(E0), rel(F, F0), np.abs(W - W0).max() / abs(E0)
     print(f"ad {sys.name} K={mesh} p={order} {precision}: dE={dE:.2e} dF={dF:.2e} dW={dW:.2e}", flush=True)
     assert dE <= tol_e
@@ -71,6 +73,15 @@ def test_ad_fp32_config2_matches_oracle(torch_dev):
 def test_ad_full_size_fp32_matches_oracle(torch_dev):
     # the 216k system at 128^3, in the configuration the benchmark's ad leg times
     check(torch_dev, systems.workload(3).system(), 128, 5, "fp32", FP32_TOL_F, FP32_TOL_E)
+
+
+@pytest.mark.parametrize("mesh", [(256, 64, 32), (16, 128, 64)])
+def test_ad_fp32_noncubic_matches_oracle(torch_dev, mesh):
+    s = systems.water_box(100, 14.0, seed=99)
+    s.box = np.array([14.0, 18.0, 11.0])
+    s.ion_pos = np.mod(s.ion_pos, s.box)
+    s.wc_pos = np.mod(s.wc_pos, s.box)
+    check(torch_dev, s, mesh, 5, "fp32", FP32_TOL_F, FP32_TOL_E)
 
 
 def test_ad_energy_and_virial_equal_ik(torch_dev):

@@ -110,6 +110,18 @@ def test_fp64_noncubic_mesh_and_box(torch_dev):
     check_vs_pppm(torch_dev, s, (32, 64, 16), 5, "fp64", 1e-9, 1e-9, 1e-9)
 
 
+# FP32 plane-mode meshes of unequal sides: the register transforms of every
+# row length from 16 to 256 (x up to 256 points, y 16 to 128, z 16 to 128),
+# each with its fused fixed-point, separation and recombination passes
+@pytest.mark.parametrize("mesh", [(32, 64, 16), (256, 64, 32), (16, 128, 64), (128, 16, 128)])
+def test_fp32_noncubic_plane_meshes(torch_dev, mesh):
+    s = systems.water_box(100, 14.0, seed=99)
+    s.box = np.array([14.0, 18.0, 11.0])
+    s.ion_pos = np.mod(s.ion_pos, s.box)
+    s.wc_pos = np.mod(s.wc_pos, s.box)
+    check_vs_pppm(torch_dev, s, mesh, 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
+
+
 def test_fp64_refined_matches_ewald_1e9(torch_dev, ewald):
     s = systems.workload(1).system()
     E, fi, fw, W, _ = run_gpu(torch_dev, s, 64, 8, "fp64")
