@@ -155,8 +155,11 @@ int64_t dplr_lr_workspace_bytes(dplr_lr_plan p);
  *                         (kx slowest, y fastest);
  *   DPLR_LR_BUF_INFLUENCE FP64 influence table G(|nx|,|ny|,|nz|),
  *                         [Kx/2+1][Ky/2+1][Kz/2+1];
- *   DPLR_LR_BUF_FIELD_SPECTRA after the inverse z and y transforms,
- *                         complex [3][Kx/2+1][Kz][Ky].
+ *   DPLR_LR_BUF_FIELD_SPECTRA the field spectra after the inverse z
+ *                         transform, complex [3][Kx/2+1][Kz][Ky] (plans
+ *                         whose z planes do not fit in LDS also apply the
+ *                         inverse y transform here; DPLR_LR_DIFF_AD plans
+ *                         fill only the first, the potential).
  * Copies `bytes` bytes (at most the buffer size, else E_INVALID) into the
  * device pointer dst, stream-ordered. */
 #define DPLR_LR_BUF_SPECTRUM 0

@@ -662,7 +662,10 @@ __global__ void __launch_bounds__(512) k_spread_fftx(const T4<T>* __restrict__ s
 // The plane is then converted to complex row pairs, transformed along x
 // (real-to-complex, two rows per complex FFT), rearranged to [kx][y] and
 // transformed along y, and written as spec[kx][z][y] (one partial spectrum
-// per split; the z pass adds them in split order).
+// per split; the z pass adds them in split order).  Where the register
+// transforms apply, the conversion (with the x-overhang fold) is the x
+// transform's first read, the rearrangement the y transform's first read,
+// and the y transform's last write goes straight to spec.
 // ----------------------------------------------------------------------------
 template <typename T, int P>
 __global__ void __launch_bounds__(1024) k_spread_xy(const T4<T>* __restrict__ sorted,
