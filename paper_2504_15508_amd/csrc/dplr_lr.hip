@@ -482,7 +482,7 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
   if (p->ixy) {
     ProfScope ps(p, 10);
     hipLaunchKernelGGL((k_ifft_xy<T>), dim3(ncomp * g.K[2]), dim3(p->thr_ixy), p->lds_ixy, s, fspec,
-                       reinterpret_cast<T*>(p->field), ncomp, tw, g, (const double*)p->partials,
+                       reinterpret_cast<T*>(p->field), ncomp, ad ? kGatherAdPad : 0, tw, g, (const double*)p->partials,
                        p->cfg.coulomb_k / (2.0 * V), energy, want_virial ? virial : (double*)nullptr);
   } else {
     ProfScope ps(p, 6);
@@ -504,8 +504,11 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
       const int nblk = (nchunks + kXcd - 1) / kXcd * kXcd;
       const int acc = (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0;
       if (ad) {
-        hipLaunchKernelGGL((k_gather_ad<T, P>), dim3(nblk), dim3(256), 0, s, reinterpret_cast<const T*>(p->field),
-                           sorted, p->sidx, p->perm, (int)n, nchunks, (T*)ion_force, (T*)wc_force, n_ion,
+        // one particle per lane, chunks of 256 sorted particles
+        const int nch = (int)((n + 255) / 256);
+        const int nb = (nch + kXcd - 1) / kXcd * kXcd;
+        hipLaunchKernelGGL((k_gather_ad<T, P>), dim3(nb), dim3(256), 0, s, reinterpret_cast<const T*>(p->field),
+                           sorted, p->sidx, p->perm, (int)n, nch, (T*)ion_force, (T*)wc_force, n_ion,
                            (T)(p->cfg.coulomb_k / V), (T)(g.K[0] / p->box[0]), (T)(g.K[1] / p->box[1]),
                            (T)(g.K[2] / p->box[2]), acc, kXcd, g);
       } else {
@@ -616,7 +619,10 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
   DPLR_ALLOC(p->spec, cs * nspec * g.nsplit, "spectrum (one partial per particle split)");
   DPLR_ALLOC(p->qmax, sizeof(unsigned) * (size_t)std::max(p->max_chunks, 1), "charge maxima");
   DPLR_ALLOC(p->fspec, 3 * cs * nspec, "field spectra");
-  DPLR_ALLOC(p->field, 3 * ts * (size_t)g.K[0] * g.K[1] * g.K[2], "fields");
+  // three interleaved field components, or (analytic differentiation) the
+  // potential in rows padded by kGatherAdPad
+  DPLR_ALLOC(p->field, ts * std::max<size_t>(3 * (size_t)g.K[0], (size_t)g.K[0] + kGatherAdPad) * g.K[1] * g.K[2],
+             "fields");
   DPLR_ALLOC(p->G, sizeof(double) * ng, "influence");
   DPLR_ALLOC(p->partials, sizeof(double) * 8 * g.nzblk, "partials");
   DPLR_ALLOC(p->twiddle, cs * g.twN, "twiddles");

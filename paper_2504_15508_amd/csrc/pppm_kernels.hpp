@@ -1183,7 +1183,7 @@ __global__ void __launch_bounds__(512) k_ifftx(const cpx<T>* __restrict__ fspec,
 // ----------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(1024) k_ifft_xy(const cpx<T>* __restrict__ fspec, T* __restrict__ field,
-                                                  int ncomp, const cpx<T>* __restrict__ twg, Geo g,
+                                                  int ncomp, int xpad, const cpx<T>* __restrict__ twg, Geo g,
                                                   const double* __restrict__ partials, double pre,
                                                   double* __restrict__ energy, double* __restrict__ virial) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1268,13 +1268,17 @@ __global__ void __launch_bounds__(1024) k_ifft_xy(const cpx<T>* __restrict__ fsp
   }
 
   // real rows (y even in the real parts, y odd in the imaginary parts) to
-  // component a of the field records (ncomp values per mesh point),
-  // consecutive threads on consecutive x
+  // component a of the field records (ncomp values per mesh point; rows of
+  // Kx + xpad records, the last xpad repeating x = 0 .. xpad-1), consecutive
+  // threads on consecutive x
   const T* tr = reinterpret_cast<const T*>(tx);
-  T* out = field + (size_t)z * Ky * Kx * ncomp + a;
+  const int RX = Kx + xpad;
+  T* out = field + (size_t)z * Ky * RX * ncomp + a;
   for (int e = threadIdx.x; e < Ky * Kx; e += blockDim.x) {
     const int y = e >> lkx, x = e & (Kx - 1);
-    out[(size_t)e * ncomp] = tr[2 * (imul(y >> 1, RS) + lds_pad(x)) + (y & 1)];
+    const T v = tr[2 * (imul(y >> 1, RS) + lds_pad(x)) + (y & 1)];
+    out[(size_t)(imul(y, RX) + x) * ncomp] = v;
+    if (x < xpad) out[(size_t)(imul(y, RX) + Kx + x) * ncomp] = v;
   }
   if (energy && blockIdx.x == 0) {
     __syncthreads();
@@ -1378,96 +1382,115 @@ __global__ void __launch_bounds__(256) DPLR_GATHER_OCC k_gather(const F3<T>* __r
 // ----------------------------------------------------------------------------
 // Forces by analytic differentiation: F_ja = -(k_e q_j / (V h_a)) times
 // sum_g phi(g) dW(u_j - g)/du_a, with the potential phi read as one value per
-// mesh point.  P lanes serve one particle as in k_gather (lane tx reads the
-// column s_x + tx of all P x P (y, z) rows) and keep three partial sums:
-// phi wy wz (for the x derivative), phi wy' wz and phi wy wz' (for y and z),
-// which the lane then weights by wx' or wx before the sums over the group.
+// mesh point.  One lane serves one particle.  Each of its P x P stencil rows
+// is read as the NC aligned 16-byte chunks that cover x = s_x .. s_x+P-1
+// (from a = s_x rounded down to a chunk boundary), and the x weights are
+// shifted by o = s_x - a once per particle instead (zero outside the
+// stencil), so the row needs no data shuffling.  The potential's rows hold
+// kGatherAdPad extra values repeating x = 0, 1, ..., so no read wraps in x.
+// Per row the lane forms rx = sum wx' phi and rw = sum wx phi
+// and adds wy wz rx, wy' wz rw and wy wz' rw to the three components.
 // ----------------------------------------------------------------------------
+template <typename T>
+struct __attribute__((aligned(16))) Chunk16 {
+  T v[16 / sizeof(T)];
+};
+
+// x padding of the potential's rows: covers the chunks of any stencil of up
+// to 8 points that starts at x <= Kx - 1 (and keeps rows 16-byte aligned)
+constexpr int kGatherAdPad = 8;
+
 template <typename T, int P>
 __global__ void __launch_bounds__(256) k_gather_ad(const T* __restrict__ phi, const T4<T>* __restrict__ sorted,
                                                    const int* __restrict__ sidx, const int* __restrict__ perm,
                                                    int n, int nchunks, T* __restrict__ ion_f, T* __restrict__ wc_f,
                                                    int64_t n_ion, T fscale, T ihx, T ihy, T ihz, int accumulate,
                                                    int nxcd, Geo g) {
+  constexpr int C = 16 / (int)sizeof(T);      // values per chunk
+  constexpr int NC = (P + 2 * C - 2) / C;     // chunks covering P values at any offset < C
+  constexpr int NW = NC * C;
   const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2];
-  constexpr int GPW = 64 / P;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grp = lane / P, tx = lane - grp * P;
-  const bool lane_on = grp < GPW;
-  const int per_block = (blockDim.x >> 6) * GPW;
+  // XCD-aware order as in k_gather: consecutive chunks of blockDim.x sorted
+  // particles go to the same XCD
   const int per_xcd = gridDim.x / nxcd;
   const int chunk = (blockIdx.x % nxcd) * per_xcd + blockIdx.x / nxcd;
-  const int v = chunk * per_block + wave * GPW + grp;
-  const bool on = lane_on && chunk < nchunks && v < n;
-  T mine[3] = {(T)0, (T)0, (T)0};
-  int src = 0;
-  if (on) {
-    const T4<T> pt = sorted[v];
-    const int sp = sidx[v];
-    src = perm[v];
-    const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
-    T wy[P], wz[P], dy[P], dz[P], wxt, dxt;
-    bspline_weight_at<T, P>(pt.x, tx, wxt, dxt);  // this lane's column only
-    bspline_weights<T, P>(pt.y, wy);
-    bspline_weights<T, P>(pt.z, wz);
-    bspline_dweights<T, P>(pt.y, dy);
-    bspline_dweights<T, P>(pt.z, dz);
-    int gx = sx + tx;
-    if (gx >= Kx) gx -= Kx;
-    T s0 = (T)0, s1 = (T)0, s2 = (T)0;
-    constexpr int TZB = (P <= 5) ? P : ((P <= 6) ? 3 : 2);
+  const int v = chunk * blockDim.x + threadIdx.x;
+  if (chunk >= nchunks || v >= n) return;
+  const T4<T> pt = sorted[v];
+  const int sp = sidx[v];
+  const int src = perm[v];
+  const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
+  T wy[P], wz[P], dy[P], dz[P];
+  bspline_weights<T, P>(pt.y, wy);
+  bspline_weights<T, P>(pt.z, wz);
+  bspline_dweights<T, P>(pt.y, dy);
+  bspline_dweights<T, P>(pt.z, dz);
+  const int xa = sx & ~(C - 1), o = sx - xa;
+  T swx[NW], sdx[NW];  // x weights shifted by o
+  {
+    T wx[P], dx[P];
+    bspline_weights<T, P>(pt.x, wx);
+    bspline_dweights<T, P>(pt.x, dx);
 #pragma unroll
-    for (int tz0 = 0; tz0 < P; tz0 += TZB) {
-      T r[TZB][P];
+    for (int j = 0; j < NW; ++j) {
+      T a = (T)0, b = (T)0;
 #pragma unroll
-      for (int d = 0; d < TZB; ++d) {
-        if (tz0 + d < P) {
-          int gz = sz + tz0 + d;
-          if (gz >= Kz) gz -= Kz;
-          const T* fz = phi + (unsigned)imul(gz, Ky) * (unsigned)Kx + gx;
-#pragma unroll
-          for (int ty = 0; ty < P; ++ty) {
-            int gy = sy + ty;
-            if (gy >= Ky) gy -= Ky;
-            r[d][ty] = fz[imul(gy, Kx)];
-          }
+      for (int oo = 0; oo < C; ++oo) {
+        if (j - oo >= 0 && j - oo < P) {
+          a = (o == oo) ? wx[j - oo] : a;
+          b = (o == oo) ? dx[j - oo] : b;
         }
       }
+      swx[j] = a;
+      sdx[j] = b;
+    }
+  }
+  static_assert(NW - C <= kGatherAdPad, "row padding too small for this order");
+  const int RX = Kx + kGatherAdPad;
+  T fx = (T)0, fy = (T)0, fz = (T)0;
+  // one plane at a time (not unrolled, so that only its rows are in flight)
+#pragma unroll 1
+  for (int tz = 0; tz < P; ++tz) {
+    T wzt = wz[0], dzt = dz[0];
 #pragma unroll
-      for (int d = 0; d < TZB; ++d) {
-        if (tz0 + d < P) {
-          const int tz = tz0 + d;
-          T a0 = (T)0, a1 = (T)0;
+    for (int k = 1; k < P; ++k) {
+      wzt = (tz == k) ? wz[k] : wzt;
+      dzt = (tz == k) ? dz[k] : dzt;
+    }
+    int gz = sz + tz;
+    if (gz >= Kz) gz -= Kz;
+    const T* plane = phi + (size_t)gz * Ky * RX;
+    T f[P][NW];
 #pragma unroll
-          for (int ty = 0; ty < P; ++ty) {
-            a0 += wy[ty] * r[d][ty];
-            a1 += dy[ty] * r[d][ty];
-          }
-          s0 += wz[tz] * a0;
-          s1 += wz[tz] * a1;
-          s2 += dz[tz] * a0;
-        }
+    for (int ty = 0; ty < P; ++ty) {
+      int gy = sy + ty;
+      if (gy >= Ky) gy -= Ky;
+      const Chunk16<T>* row = reinterpret_cast<const Chunk16<T>*>(plane + (size_t)gy * RX + xa);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const Chunk16<T> ch = row[c];
+#pragma unroll
+        for (int k = 0; k < C; ++k) f[ty][c * C + k] = ch.v[k];
       }
     }
-    const T qs = -fscale * pt.w;
-    mine[0] = qs * ihx * dxt * s0;
-    mine[1] = qs * ihy * wxt * s1;
-    mine[2] = qs * ihz * wxt * s2;
-  }
-  const int gbase = grp * P;
-  T tot[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    T s = (T)0;
+    for (int ty = 0; ty < P; ++ty) {
+      T rx = (T)0, rw = (T)0;
 #pragma unroll
-    for (int k = 0; k < P; ++k) s += __shfl(mine[a], gbase + k, 64);
-    tot[a] = s;
+      for (int j = 0; j < NW; ++j) {
+        rx += sdx[j] * f[ty][j];
+        rw += swx[j] * f[ty][j];
+      }
+      fx += wy[ty] * wzt * rx;
+      fy += dy[ty] * wzt * rw;
+      fz += wy[ty] * dzt * rw;
+    }
   }
-  if (on && tx == 0) {
-    T* out = (src < n_ion) ? (ion_f + 3 * (int64_t)src) : (wc_f + 3 * ((int64_t)src - n_ion));
+  const T qs = -fscale * pt.w;
+  const T tot[3] = {qs * ihx * fx, qs * ihy * fy, qs * ihz * fz};
+  T* out = (src < n_ion) ? (ion_f + 3 * (int64_t)src) : (wc_f + 3 * ((int64_t)src - n_ion));
 #pragma unroll
-    for (int a = 0; a < 3; ++a) out[a] = accumulate ? out[a] + tot[a] : tot[a];
-  }
+  for (int a = 0; a < 3; ++a) out[a] = accumulate ? out[a] + tot[a] : tot[a];
 }
 
 // ----------------------------------------------------------------------------
