@@ -503,7 +503,7 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
       const int nchunks = (int)((n + per_block - 1) / per_block);
       const int nblk = (nchunks + kXcd - 1) / kXcd * kXcd;
       const int acc = (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0;
-      if (ad) {
+      if (ad && P <= 6) {
         // one particle per lane, chunks of 256 sorted particles
         const int nch = (int)((n + 255) / 256);
         const int nb = (nch + kXcd - 1) / kXcd * kXcd;
@@ -511,6 +511,11 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
                            sorted, p->sidx, p->perm, (int)n, nch, (T*)ion_force, (T*)wc_force, n_ion,
                            (T)(p->cfg.coulomb_k / V), (T)(g.K[0] / p->box[0]), (T)(g.K[1] / p->box[1]),
                            (T)(g.K[2] / p->box[2]), acc, kXcd, g);
+      } else if (ad) {
+        hipLaunchKernelGGL((k_gather_ad_lanes<T, P>), dim3(nblk), dim3(256), 0, s,
+                           reinterpret_cast<const T*>(p->field), sorted, p->sidx, p->perm, (int)n, nchunks,
+                           (T*)ion_force, (T*)wc_force, n_ion, (T)(p->cfg.coulomb_k / V), (T)(g.K[0] / p->box[0]),
+                           (T)(g.K[1] / p->box[1]), (T)(g.K[2] / p->box[2]), acc, kXcd, g);
       } else {
         hipLaunchKernelGGL((k_gather<T, P>), dim3(nblk), dim3(256), 0, s, reinterpret_cast<const F3<T>*>(p->field),
                            sorted, p->sidx, p->perm, (int)n, nchunks, (T*)ion_force, (T*)wc_force, n_ion,

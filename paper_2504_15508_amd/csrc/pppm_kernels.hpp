@@ -1494,6 +1494,102 @@ __global__ void __launch_bounds__(256) k_gather_ad(const T* __restrict__ phi, co
 }
 
 // ----------------------------------------------------------------------------
+// The same forces with P lanes per particle (used for orders above 6, where
+// one lane would hold too many stencil rows in flight): lane tx reads the
+// column s_x + tx of all P x P (y, z) rows of the padded potential and keeps
+// three partial sums, phi wy wz (for the x derivative), phi wy' wz and
+// phi wy wz' (for y and z), which it then weights by wx' or wx before the
+// sums over the group.
+// ----------------------------------------------------------------------------
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_gather_ad_lanes(const T* __restrict__ phi, const T4<T>* __restrict__ sorted,
+                                                   const int* __restrict__ sidx, const int* __restrict__ perm,
+                                                   int n, int nchunks, T* __restrict__ ion_f, T* __restrict__ wc_f,
+                                                   int64_t n_ion, T fscale, T ihx, T ihy, T ihz, int accumulate,
+                                                   int nxcd, Geo g) {
+  const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2];
+  const int RX = Kx + kGatherAdPad;
+  constexpr int GPW = 64 / P;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / P, tx = lane - grp * P;
+  const bool lane_on = grp < GPW;
+  const int per_block = (blockDim.x >> 6) * GPW;
+  const int per_xcd = gridDim.x / nxcd;
+  const int chunk = (blockIdx.x % nxcd) * per_xcd + blockIdx.x / nxcd;
+  const int v = chunk * per_block + wave * GPW + grp;
+  const bool on = lane_on && chunk < nchunks && v < n;
+  T mine[3] = {(T)0, (T)0, (T)0};
+  int src = 0;
+  if (on) {
+    const T4<T> pt = sorted[v];
+    const int sp = sidx[v];
+    src = perm[v];
+    const int sx = sp & 1023, sy = (sp >> 10) & 1023, sz = sp >> 20;
+    T wy[P], wz[P], dy[P], dz[P], wxt, dxt;
+    bspline_weight_at<T, P>(pt.x, tx, wxt, dxt);  // this lane's column only
+    bspline_weights<T, P>(pt.y, wy);
+    bspline_weights<T, P>(pt.z, wz);
+    bspline_dweights<T, P>(pt.y, dy);
+    bspline_dweights<T, P>(pt.z, dz);
+    int gx = sx + tx;
+    if (gx >= Kx) gx -= Kx;
+    T s0 = (T)0, s1 = (T)0, s2 = (T)0;
+    constexpr int TZB = (P <= 5) ? P : ((P <= 6) ? 3 : 2);
+#pragma unroll
+    for (int tz0 = 0; tz0 < P; tz0 += TZB) {
+      T r[TZB][P];
+#pragma unroll
+      for (int d = 0; d < TZB; ++d) {
+        if (tz0 + d < P) {
+          int gz = sz + tz0 + d;
+          if (gz >= Kz) gz -= Kz;
+          const T* fz = phi + (size_t)gz * Ky * RX + gx;
+#pragma unroll
+          for (int ty = 0; ty < P; ++ty) {
+            int gy = sy + ty;
+            if (gy >= Ky) gy -= Ky;
+            r[d][ty] = fz[imul(gy, RX)];
+          }
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < TZB; ++d) {
+        if (tz0 + d < P) {
+          const int tz = tz0 + d;
+          T a0 = (T)0, a1 = (T)0;
+#pragma unroll
+          for (int ty = 0; ty < P; ++ty) {
+            a0 += wy[ty] * r[d][ty];
+            a1 += dy[ty] * r[d][ty];
+          }
+          s0 += wz[tz] * a0;
+          s1 += wz[tz] * a1;
+          s2 += dz[tz] * a0;
+        }
+      }
+    }
+    const T qs = -fscale * pt.w;
+    mine[0] = qs * ihx * dxt * s0;
+    mine[1] = qs * ihy * wxt * s1;
+    mine[2] = qs * ihz * wxt * s2;
+  }
+  const int gbase = grp * P;
+  T tot[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    T s = (T)0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) s += __shfl(mine[a], gbase + k, 64);
+    tot[a] = s;
+  }
+  if (on && tx == 0) {
+    T* out = (src < n_ion) ? (ion_f + 3 * (int64_t)src) : (wc_f + 3 * ((int64_t)src - n_ion));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a] = accumulate ? out[a] + tot[a] : tot[a];
+  }
+}
+
+// ----------------------------------------------------------------------------
 // FP64 optimal influence function for ik-differentiation (per box).
 //   G(k) = sum_m (k.k_m) U^2(k_m) phi(k_m) / (|k|^2 [sum_m U^2(k_m)]^2),
 //   k_m = k + 2 pi m / h, U(k) = prod_a sinc(k_a h_a / 2)^p,
