@@ -71,9 +71,7 @@ typedef enum { DPLR_LR_FP32 = 0, DPLR_LR_FP64 = 1 } dplr_lr_precision;
  *   F_ja = -(k_e q_j / (V h_a)) sum_g phi(g) dW(u_j - g)/du_a
  * is the exact gradient of the returned energy (same E and virial as ik).
  * Not the paper's choice (it uses Poisson-IK); the adjacent textbook
- * variant.  The net force is not exactly zero.  Needs z planes that fit in
- * LDS (Kx * Ky <= 16384 at FP32); otherwise plan creation returns
- * DPLR_LR_E_UNSUPPORTED. */
+ * variant.  The net force is not exactly zero. */
 #define DPLR_LR_DIFF_AD    0x4u
 
 typedef struct {

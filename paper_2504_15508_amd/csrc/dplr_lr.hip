@@ -486,7 +486,7 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
                        p->cfg.coulomb_k / (2.0 * V), energy, want_virial ? virial : (double*)nullptr);
   } else {
     ProfScope ps(p, 6);
-    hipLaunchKernelGGL((k_ffty<T, true>), dim3(3 * g.Kh * (g.K[2] / g.zb)), dim3(p->thr_ffty), p->lds_ffty, s,
+    hipLaunchKernelGGL((k_ffty<T, true>), dim3(ncomp * g.Kh * (g.K[2] / g.zb)), dim3(p->thr_ffty), p->lds_ffty, s,
                        fspec, tw, g, 1, (size_t)0, (const double*)p->partials, p->cfg.coulomb_k / (2.0 * V), energy,
                        want_virial ? virial : (double*)nullptr);
   }
@@ -494,7 +494,7 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
     if (!p->ixy) {
       ProfScope ps(p, 7);
       hipLaunchKernelGGL((k_ifftx<T>), dim3(g.K[2] * (g.K[1] / g.xyb)), dim3(p->thr_ifftx), p->lds_ifftx, s, fspec,
-                         reinterpret_cast<F3<T>*>(p->field), tw, g);
+                         reinterpret_cast<T*>(p->field), ncomp, tw, g);
     }
     {
       ProfScope ps(p, 8);
@@ -595,11 +595,6 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
   if (!choose_geometry(p)) {
     delete p;
     return fail(nullptr, DPLR_LR_E_UNSUPPORTED, "no tiling fits the device's LDS for this mesh/order/precision");
-  }
-  if ((cfg->flags & DPLR_LR_DIFF_AD) && !p->ixy) {
-    delete p;
-    return fail(nullptr, DPLR_LR_E_UNSUPPORTED,
-                "analytic differentiation needs z planes that fit in LDS (Kx * Ky <= 16384 here)");
   }
   const Geo& g = p->geo;
   const size_t ts = p->tsize, cs = 2 * ts;

@@ -1105,13 +1105,21 @@ struct F3 {
   T x, y, z;
 };
 
+// x padding of the potential's rows (analytic differentiation): covers the
+// 16-byte chunks of any stencil of up to 8 points that starts at x <= Kx - 1
+// (and keeps rows 16-byte aligned)
+constexpr int kGatherAdPad = 8;
+
+// ncomp = 3 writes the interleaved field records; ncomp = 1 (analytic
+// differentiation) writes the potential in rows of Kx + kGatherAdPad values,
+// the last ones repeating x = 0, 1, ...
 template <typename T>
-__global__ void __launch_bounds__(512) k_ifftx(const cpx<T>* __restrict__ fspec, F3<T>* __restrict__ field,
+__global__ void __launch_bounds__(512) k_ifftx(const cpx<T>* __restrict__ fspec, T* __restrict__ field, int ncomp,
                                                const cpx<T>* __restrict__ twg, Geo g) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2], Kh = g.Kh;
   const int yb = g.xyb;                  // y rows per block
-  const int nrc = (3 * yb) / 2;          // complex rows: pair (2c, 2c+1) of rows r = a*yb + yl
+  const int nrc = (ncomp * yb) / 2;      // complex rows: pair (2c, 2c+1) of rows r = a*yb + yl
   const int RS = padded_len(Kx) + 1;
   cpx<T>* tile = reinterpret_cast<cpx<T>*>(smem);  // [nrc][RS]
   cpx<T>* tw = tile + (size_t)nrc * RS;
@@ -1151,18 +1159,29 @@ __global__ void __launch_bounds__(512) k_ifftx(const cpx<T>* __restrict__ fspec,
 
   // store: record (yl, x) gathers component a from row r = a*yb + yl
   const T* tr = reinterpret_cast<const T*>(tile);
-  F3<T>* out = field + ((size_t)z * Ky + y0) * Kx;
   const int lkx = 31 - __clz(Kx);
-  for (int e = threadIdx.x; e < yb * Kx; e += blockDim.x) {
-    const int yl = e >> lkx, x = e & (Kx - 1);
-    const int col = 2 * lds_pad(x);
-    T v[3];
+  if (ncomp == 3) {
+    F3<T>* out = reinterpret_cast<F3<T>*>(field) + ((size_t)z * Ky + y0) * Kx;
+    for (int e = threadIdx.x; e < yb * Kx; e += blockDim.x) {
+      const int yl = e >> lkx, x = e & (Kx - 1);
+      const int col = 2 * lds_pad(x);
+      T v[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int r = a * yb + yl;
-      v[a] = tr[2 * imul(r >> 1, RS) + col + (r & 1)];
+      for (int a = 0; a < 3; ++a) {
+        const int r = a * yb + yl;
+        v[a] = tr[2 * imul(r >> 1, RS) + col + (r & 1)];
+      }
+      out[e] = F3<T>{v[0], v[1], v[2]};
     }
-    out[e] = F3<T>{v[0], v[1], v[2]};
+  } else {
+    const int RX = Kx + kGatherAdPad;
+    T* out = field + ((size_t)z * Ky + y0) * RX;
+    for (int e = threadIdx.x; e < yb * Kx; e += blockDim.x) {
+      const int yl = e >> lkx, x = e & (Kx - 1);
+      const T v = tr[2 * imul(yl >> 1, RS) + 2 * lds_pad(x) + (yl & 1)];
+      out[imul(yl, RX) + x] = v;
+      if (x < kGatherAdPad) out[imul(yl, RX) + Kx + x] = v;
+    }
   }
 }
 
@@ -1396,9 +1415,7 @@ struct __attribute__((aligned(16))) Chunk16 {
   T v[16 / sizeof(T)];
 };
 
-// x padding of the potential's rows: covers the chunks of any stencil of up
-// to 8 points that starts at x <= Kx - 1 (and keeps rows 16-byte aligned)
-constexpr int kGatherAdPad = 8;
+
 
 template <typename T, int P>
 __global__ void __launch_bounds__(256) k_gather_ad(const T* __restrict__ phi, const T4<T>* __restrict__ sorted,

@@ -126,8 +126,8 @@ def test_ad_forces_are_the_gradient_of_the_plan_energy(torch_dev):
     assert worst_ik > 1e-4
 
 
-def test_ad_needs_planes_in_lds(torch_dev):
-    import paper_2504_15508_amd as dl
-    with pytest.raises(dl.DplrError) as ei:
-        dl.Plan((256, 128, 16), order=5, precision="fp32", capacity=10, diff="ad")
-    assert "E_UNSUPPORTED" in str(ei.value)
+# meshes whose z planes do not fit in LDS: pencil spread, separate inverse y
+# and x passes writing the padded potential
+@pytest.mark.parametrize("precision,tol_f,tol_e", [("fp64", 1e-10, 1e-10), ("fp32", FP32_TOL_F, FP32_TOL_E)])
+def test_ad_pencil_path_matches_oracle(torch_dev, precision, tol_f, tol_e):
+    check(torch_dev, systems.workload(1).system(), (256, 128, 16), 5, precision, tol_f, tol_e)
