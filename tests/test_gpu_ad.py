@@ -126,6 +126,15 @@ def test_ad_forces_are_the_gradient_of_the_plan_energy(torch_dev):
     assert worst_ik > 1e-4
 
 
+def test_ad_longest_rows_match_oracle(torch_dev):
+    # 512-point x rows: the LDS Stockham transforms and unfused passes
+    s = systems.water_box(100, 14.0, seed=99)
+    s.box = np.array([24.0, 12.0, 12.0])
+    s.ion_pos = np.mod(s.ion_pos, s.box)
+    s.wc_pos = np.mod(s.wc_pos, s.box)
+    check(torch_dev, s, (512, 16, 32), 5, "fp32", FP32_TOL_F, FP32_TOL_E)
+
+
 # meshes whose z planes do not fit in LDS: pencil spread, separate inverse y
 # and x passes writing the padded potential
 @pytest.mark.parametrize("precision,tol_f,tol_e", [("fp64", 1e-10, 1e-10), ("fp32", FP32_TOL_F, FP32_TOL_E)])

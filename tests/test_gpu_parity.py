@@ -122,6 +122,17 @@ def test_fp32_noncubic_plane_meshes(torch_dev, mesh):
     check_vs_pppm(torch_dev, s, mesh, 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
 
 
+# The longest rows (512 points) run the LDS Stockham transforms and the
+# unfused conversion, separation and recombination passes of the plane kernels
+@pytest.mark.parametrize("precision,tol_f,tol_e", [("fp64", 1e-9, 1e-9), ("fp32", 1e-5, 2e-6)])
+def test_longest_rows_match_pppm_oracle(torch_dev, precision, tol_f, tol_e):
+    s = systems.water_box(100, 14.0, seed=99)
+    s.box = np.array([24.0, 12.0, 12.0])
+    s.ion_pos = np.mod(s.ion_pos, s.box)
+    s.wc_pos = np.mod(s.wc_pos, s.box)
+    check_vs_pppm(torch_dev, s, (512, 16, 32), 5, precision, tol_f, tol_e, tol_e)
+
+
 def test_fp64_refined_matches_ewald_1e9(torch_dev, ewald):
     s = systems.workload(1).system()
     E, fi, fw, W, _ = run_gpu(torch_dev, s, 64, 8, "fp64")
