@@ -1,0 +1,67 @@
+"""Seeded random configurations against the oracles: mesh sides (powers of two
+16..128, unequal), assignment order 2..8, box edges 9..30 A, particle counts,
+non-neutral charge sets, FP64 and FP32, ik and ad.  Every case is checked
+element by element against the FP64 PPPM oracle of the same scheme."""
+import numpy as np
+import pytest
+
+import systems
+from oracle import pppm
+
+pytestmark = pytest.mark.gpu
+
+KE = systems.COULOMB_K
+BETA = systems.BETA
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    return torch
+
+
+def case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    mesh = tuple(int(2 ** rng.integers(4, 8)) for _ in range(3))
+    order = int(rng.integers(2, 9))
+    box = rng.uniform(9.0, 30.0, 3)
+    n_ion, n_wc = int(rng.integers(1, 400)), int(rng.integers(0, 150))
+    pos_i = rng.uniform(-0.5, 1.5, (n_ion, 3)) * box      # some outside the box
+    pos_w = rng.uniform(0.0, 1.0, (n_wc, 3)) * box
+    q_i = rng.choice([6.0, 1.0, 1.0, -1.0, 0.5], n_ion)
+    q_w = np.full(n_wc, -8.0)
+    precision = "fp64" if seed % 2 == 0 else "fp32"
+    diff = "ad" if seed % 3 == 0 else "ik"
+    return mesh, order, box, pos_i, q_i, pos_w, q_w, precision, diff
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_configuration_matches_oracle(torch_dev, seed):
+    torch = torch_dev
+    import paper_2504_15508_amd as dl
+    mesh, order, box, pos_i, q_i, pos_w, q_w, precision, diff = case(seed)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    plan = dl.Plan(mesh, order=order, beta=BETA, coulomb_k=KE, precision=precision,
+                   capacity=len(q_i) + len(q_w), diff=diff)
+    plan.set_box(box)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    E, fi, fw, W = plan.compute(t(pos_i), t(q_i), t(pos_w), t(q_w))
+    torch.cuda.synchronize()
+    F = np.concatenate([fi.double().cpu().numpy(), fw.double().cpu().numpy()])
+    r = (lambda a: np.asarray(a, np.float32).astype(np.float64)) if precision == "fp32" else np.asarray
+    pos = np.concatenate([r(pos_i), r(pos_w)])
+    q = np.concatenate([r(q_i), r(q_w)])
+    fn = pppm.pppm_ad if diff == "ad" else pppm.pppm
+    E0, F0, W0 = fn(pos, q, box, mesh, order, BETA, KE)
+    tol_f, tol_e = (1e-9, 1e-9) if precision == "fp64" else (1e-5, 2e-6)
+    dF = float(np.linalg.norm(F - F0) / np.linalg.norm(F0))
+    dE = abs(float(E) - E0) / abs(E0)
+    dW = float(np.abs(W.cpu().numpy() - W0).max() / abs(E0))
+    print(f"seed {seed} {mesh} p={order} {precision} {diff} n={len(q)}: dE={dE:.2e} dF={dF:.2e} dW={dW:.2e}",
+          flush=True)
+    plan.close()
+    assert dF <= tol_f
+    assert dE <= tol_e
+    assert dW <= tol_e
