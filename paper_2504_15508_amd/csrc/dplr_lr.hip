@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "pppm_kernels.hpp"
+#include "mixed_radix_kernels.hpp"
 
 using namespace dplr;
 
@@ -71,6 +72,22 @@ constexpr int kMinOrder = 2;
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// sizes with no prime factor other than 2, 3 and 5
+bool is_235(int v) {
+  if (v <= 0) return false;
+  for (int f : {2, 3, 5})
+    while (v % f == 0) v /= f;
+  return v == 1;
+}
+
+// The plane/pencil kernels take power-of-two meshes of 16 to 512 points per
+// axis; other 2-3-5 meshes run on the mixed-radix kernels.
+bool tuned_mesh(const int* K) {
+  for (int a = 0; a < 3; ++a)
+    if (!is_pow2(K[a]) || K[a] < kMinMesh || K[a] > kMaxMesh) return false;
+  return true;
+}
+
 int round_threads(long elems) {
   long t = (elems + kEPT - 1) / kEPT;
   t = ((t + 63) / 64) * 64;
@@ -83,14 +100,26 @@ dplr_lr_status validate(const dplr_lr_config* c, std::string& msg) {
   if (!c) { msg = "config is NULL"; return DPLR_LR_E_INVALID; }
   for (int a = 0; a < 3; ++a) {
     if (c->mesh[a] <= 0) { msg = "mesh sizes must be positive"; return DPLR_LR_E_INVALID; }
-    if (!is_pow2(c->mesh[a]) || c->mesh[a] < kMinMesh || c->mesh[a] > kMaxMesh) {
-      msg = "mesh sizes must be powers of two in [16, 512]";
+    if (!is_235(c->mesh[a]) || c->mesh[a] > kMaxMesh) {
+      msg = "mesh sizes must have no prime factors other than 2, 3 and 5 and be at most 512";
       return DPLR_LR_E_UNSUPPORTED;
     }
   }
   if (c->order < kMinOrder || c->order > kMaxOrder) {
     msg = "order must be in [2, 8]";
     return c->order <= 0 ? DPLR_LR_E_INVALID : DPLR_LR_E_UNSUPPORTED;
+  }
+  if (!tuned_mesh(c->mesh)) {
+    for (int a = 0; a < 3; ++a) {
+      if (c->mesh[a] < c->order) {
+        msg = "mesh sizes below 16 or not powers of two must be at least the order";
+        return DPLR_LR_E_UNSUPPORTED;
+      }
+    }
+    if (c->flags & DPLR_LR_DIFF_AD) {
+      msg = "analytic differentiation needs power-of-two meshes of 16 to 512 points";
+      return DPLR_LR_E_UNSUPPORTED;
+    }
   }
   if (!(c->beta > 0.0) || !std::isfinite(c->beta)) { msg = "beta must be positive and finite"; return DPLR_LR_E_INVALID; }
   if (!std::isfinite(c->coulomb_k)) { msg = "coulomb_k must be finite"; return DPLR_LR_E_INVALID; }
@@ -119,6 +148,11 @@ struct dplr_lr_plan_s {
   size_t lds_spread = 0, lds_ffty = 0, lds_z = 0, lds_ifftx = 0, lds_ixy = 0;
   bool plane = false;         // whole z planes fit in LDS: spread + x and y transforms in one kernel
   bool ixy = false;           // inverse y and x transforms of a plane component in one kernel
+  bool mixed = false;         // mesh outside the tuned kernels: mixed-radix path
+  long long* mmesh = nullptr; // mixed-radix path: fixed-point mesh [Kz][Ky][Kx]
+  void* mspec = nullptr;      // ... its full complex spectrum
+  void* mfield = nullptr;     // ... three full field spectra, transformed back in place
+  int mblk = 0;               // ... blocks (and partials) of the ik multiply
   int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_ifftx = 256, thr_ixy = 256;
   // device workspace
   int* bin_count = nullptr;
@@ -153,8 +187,10 @@ namespace {
 
 const char* const kStageNames[] = {"bin_count", "bin_scan", "bin_scatter", "spread_fftx", "ffty_fwd",
                                    "fftz_poisson", "ffty_inv_reduce", "ifftx", "gather", "spread_xy",
-                                   "ifft_xy_reduce"};
-constexpr int kNumStages = 11;
+                                   "ifft_xy_reduce", "mixed_spread", "mixed_fft_fwd", "mixed_poisson",
+                                   "mixed_fft_inv", "mixed_gather"};
+constexpr int kNumStages = 16;
+static_assert(kNumStages <= 16, "profile slots");
 
 hipEvent_t prof_event(dplr_lr_plan p) {
   if (!p->prof_pool.empty()) {
@@ -528,9 +564,88 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
   return DPLR_LR_OK;
 }
 
+// Mixed-radix path: spread, forward x/y/z transforms, ik multiply, the three
+// inverse x/y/z transforms, energy/virial reduction, gather.
+int mixed_fft_threads(int N) { return N <= 128 ? 64 : (N <= 512 ? 128 : 256); }
+
+template <typename T>
+void launch_mixed_fft(dplr_lr_plan p, cpx<T>* data, int ncomp, int sign) {
+  const int K[3] = {p->geo.K[0], p->geo.K[1], p->geo.K[2]};
+  const int64_t ntot = (int64_t)K[0] * K[1] * K[2];
+  const int64_t stride[3] = {1, K[0], (int64_t)K[0] * K[1]};
+  for (int a = 0; a < 3; ++a) {
+    const int64_t rows = ntot / K[a];
+    hipLaunchKernelGGL(k_mixed_fft_axis<T>, dim3((unsigned)rows, (unsigned)ncomp), dim3(mixed_fft_threads(K[a])),
+                       2 * sizeof(cpx<T>) * K[a], p->stream, data, K[a], stride[a], ntot, sign);
+  }
+}
+
+template <typename T, int P>
+dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, const void* ion_q, int64_t n_wc,
+                            const void* wc_pos, const void* wc_q, void* ion_force, void* wc_force, double* energy,
+                            double* virial) {
+  const Geo& g = p->geo;
+  hipStream_t s = p->stream;
+  const int64_t n = n_ion + n_wc;
+  const int64_t ntot = (int64_t)g.K[0] * g.K[1] * g.K[2];
+  const double ih[3] = {g.K[0] / p->box[0], g.K[1] / p->box[1], g.K[2] / p->box[2]};
+  cpx<T>* spec = reinterpret_cast<cpx<T>*>(p->mspec);
+  cpx<T>* field = reinterpret_cast<cpx<T>*>(p->mfield);
+  const unsigned nbp = (unsigned)((n + 255) / 256);
+  if (n > 0) {
+    ProfScope ps(p, 11);
+    hipLaunchKernelGGL((k_mixed_spread<T, P>), dim3(nbp), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
+                       (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], g.K[0], g.K[1], g.K[2],
+                       (unsigned long long*)p->mmesh);
+  }
+  {
+    ProfScope ps(p, 12);
+    hipLaunchKernelGGL(k_mixed_unfix<T>, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, p->mmesh, spec, ntot);
+    launch_mixed_fft<T>(p, spec, 1, -1);
+  }
+  PoissonConsts pc;
+  for (int a = 0; a < 3; ++a) pc.two_pi_over_L[a] = 2.0 * M_PI / p->box[a];
+  pc.inv_4beta2 = 1.0 / (4.0 * p->cfg.beta * p->cfg.beta);
+  const double V = p->box[0] * p->box[1] * p->box[2];
+  const bool want_virial = !(p->cfg.flags & DPLR_LR_NO_VIRIAL) && virial;
+  {
+    ProfScope ps(p, 13);
+    hipLaunchKernelGGL(k_mixed_poisson<T>, dim3((unsigned)p->mblk), dim3(256), 0, s, spec, field, p->G, g.K[0],
+                       g.K[1], g.K[2], pc, p->partials);
+    hipLaunchKernelGGL(k_mixed_reduce, dim3(1), dim3(256), 0, s, (const double*)p->partials, p->mblk,
+                       p->cfg.coulomb_k / (2.0 * V), energy, want_virial ? virial : (double*)nullptr);
+  }
+  if (n > 0) {
+    {
+      ProfScope ps(p, 14);
+      launch_mixed_fft<T>(p, field, 3, +1);
+    }
+    ProfScope ps(p, 15);
+    hipLaunchKernelGGL((k_mixed_gather<T, P>), dim3(nbp), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
+                       (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], g.K[0], g.K[1], g.K[2],
+                       (const cpx<T>*)field, (T*)ion_force, (T*)wc_force, (T)(p->cfg.coulomb_k / V),
+                       (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
+  return DPLR_LR_OK;
+}
+
 template <typename T>
 dplr_lr_status dispatch_order(dplr_lr_plan p, int64_t n_ion, const void* a, const void* b, int64_t n_wc,
                               const void* c, const void* d, void* e, void* f, double* en, double* vir) {
+  if (p->mixed) {
+    switch (p->cfg.order) {
+      case 2: return launch_mixed<T, 2>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+      case 3: return launch_mixed<T, 3>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+      case 4: return launch_mixed<T, 4>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+      case 5: return launch_mixed<T, 5>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+      case 6: return launch_mixed<T, 6>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+      case 7: return launch_mixed<T, 7>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+      case 8: return launch_mixed<T, 8>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
+    }
+    return fail(p, DPLR_LR_E_UNSUPPORTED, "order");
+  }
   switch (p->cfg.order) {
     case 2: return launch_step<T, 2>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
     case 3: return launch_step<T, 3>(p, n_ion, a, b, n_wc, c, d, e, f, en, vir);
@@ -592,6 +707,36 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
   e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
   if (e != hipSuccess) { delete p; return hip_fail(nullptr, e, "hipDeviceGetAttribute"); }
   p->lds_budget = (size_t)std::min(lds, 160 * 1024);
+  if (!tuned_mesh(cfg->mesh)) {
+    p->mixed = true;
+    Geo& g = p->geo;
+    for (int a = 0; a < 3; ++a) g.K[a] = cfg->mesh[a];
+    g.Kh = g.K[0] / 2 + 1;
+    const size_t ts = p->tsize, cs = 2 * ts;
+    const size_t ntot = (size_t)g.K[0] * g.K[1] * g.K[2];
+    const size_t ng = (size_t)g.Kh * (g.K[1] / 2 + 1) * (g.K[2] / 2 + 1);
+    p->mblk = (int)((ntot + 255) / 256);
+    dplr_lr_status sm = DPLR_LR_OK;
+    void* tmp = nullptr;
+    if (sm == DPLR_LR_OK) { sm = alloc(p, &tmp, sizeof(long long) * ntot, "mixed-radix mesh"); p->mmesh = (long long*)tmp; }
+    if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mspec, cs * ntot, "mixed-radix spectrum"); }
+    if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mfield, 3 * cs * ntot, "mixed-radix fields"); }
+    if (sm == DPLR_LR_OK) { sm = alloc(p, &tmp, sizeof(double) * ng, "influence"); p->G = (double*)tmp; }
+    if (sm == DPLR_LR_OK) { sm = alloc(p, &tmp, sizeof(double) * 8 * p->mblk, "partials"); p->partials = (double*)tmp; }
+    if (sm == DPLR_LR_OK) {
+      hipError_t e2 = hipMemset(p->mmesh, 0, sizeof(long long) * ntot);
+      if (e2 == hipSuccess) e2 = hipMemset(p->G, 0, sizeof(double) * ng);
+      if (e2 != hipSuccess) sm = hip_fail(p, e2, "workspace init");
+    }
+    if (sm != DPLR_LR_OK) {
+      g_global_error = p->err;
+      free_all(p);
+      delete p;
+      return sm;
+    }
+    *out = p;
+    return DPLR_LR_OK;
+  }
   if (!choose_geometry(p)) {
     delete p;
     return fail(nullptr, DPLR_LR_E_UNSUPPORTED, "no tiling fits the device's LDS for this mesh/order/precision");
@@ -770,6 +915,7 @@ int64_t dplr_lr_debug_size(dplr_lr_plan p, int32_t which) {
   const Geo& g = p->geo;
   const size_t cs = 2 * p->tsize;
   const size_t nspec = (size_t)g.Kh * g.K[1] * g.K[2];
+  if (p->mixed && which != DPLR_LR_BUF_INFLUENCE) return -1;
   switch (which) {
     case DPLR_LR_BUF_SPECTRUM: return (int64_t)(cs * nspec);
     case DPLR_LR_BUF_INFLUENCE: return (int64_t)(sizeof(double) * g.Kh * (g.K[1] / 2 + 1) * (g.K[2] / 2 + 1));

@@ -1,0 +1,286 @@
+// PPPM-ik on meshes whose sizes are not all powers of two.
+//
+// The paper runs its precision study on small per-node grids such as
+// 8x12x8, 10x15x10 and 12x18x12 (Results, accuracy of the precision
+// variants), which the plane/pencil kernels cannot take: those assume
+// power-of-two rows for their register transforms, bins and index masks.
+// This path computes the same steps as the tuned one (spread, forward 3D
+// transform, optimal-G ik multiply with FP64 energy/virial sums, three
+// inverse 3D transforms, gather) on any mesh whose sizes factor into 2, 3
+// and 5, with plain kernels sized for meshes of a few thousand to a few
+// million points:
+//  - spread: one thread per particle, 64-bit fixed-point global atomics
+//    (integer sums, so the mesh is bitwise repeatable);
+//  - transforms: full complex 3D transforms (the real-input symmetry is not
+//    used), one LDS-resident row per block, self-sorting (Stockham) stages
+//    of radix 4, 2, 3 and 5 with twiddles from sincospi;
+//  - ik multiply: one thread per mesh point of the full spectrum, the energy
+//    and virial summed in FP64 per block and reduced in a fixed tree;
+//  - gather: one thread per particle, in the caller's order (no sort).
+// Mesh layout: x fastest, index (z Ky + y) Kx + x, complex values of the
+// plan's precision; the three field spectra follow one another.
+#pragma once
+
+#include "pppm_kernels.hpp"
+
+namespace dplr {
+
+// Fixed-point scale of the mixed-radix spread (both precisions): 2^40, so a
+// mesh value must stay below 2^23 in charge units.
+constexpr double kMixedFixedScale = 1099511627776.0;
+
+// Stencil start s and offset d (weights M_P(d + P-1-t) at s + t) along one
+// axis, in FP64 like the tuned path; non-finite inputs map to u = 0.
+template <int P>
+__device__ __forceinline__ int mixed_stencil(double r, double invh, int K, double& d) {
+  const double Kd = (double)K;
+  double v = r * invh;
+  v = v - Kd * floor(v / Kd);
+  if (v >= Kd) v -= Kd;
+  if (!(v >= 0.0 && v < Kd)) v = 0.0;
+  const double av = v - 0.5 * P;
+  const double f = floor(av);
+  d = av - f;
+  int s = (int)f + 1;
+  if (s < 0) s += K;
+  if (s >= K) s -= K;
+  return s;
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_mixed_spread(const T* __restrict__ ion_pos, const T* __restrict__ ion_q,
+                                                      const T* __restrict__ wc_pos, const T* __restrict__ wc_q,
+                                                      int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
+                                                      int Kx, int Ky, int Kz,
+                                                      unsigned long long* __restrict__ mesh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T* r = (i < n_ion) ? (ion_pos + 3 * i) : (wc_pos + 3 * (i - n_ion));
+  const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
+  double d[3];
+  const int sx = mixed_stencil<P>((double)r[0], ihx, Kx, d[0]);
+  const int sy = mixed_stencil<P>((double)r[1], ihy, Ky, d[1]);
+  const int sz = mixed_stencil<P>((double)r[2], ihz, Kz, d[2]);
+  T wx[P], wy[P], wz[P];
+  bspline_weights<T, P>((T)d[0], wx);
+  bspline_weights<T, P>((T)d[1], wy);
+  bspline_weights<T, P>((T)d[2], wz);
+  int gx[P];
+#pragma unroll
+  for (int t = 0; t < P; ++t) gx[t] = (sx + t) % Kx;
+  for (int tz = 0; tz < P; ++tz) {
+    const int gz = (sz + tz) % Kz;
+    const T qz = q * wz[tz];
+    for (int ty = 0; ty < P; ++ty) {
+      const int gy = (sy + ty) % Ky;
+      const T qyz = qz * wy[ty];
+      unsigned long long* row = mesh + ((size_t)gz * Ky + gy) * Kx;
+#pragma unroll
+      for (int tx = 0; tx < P; ++tx) {
+        const long long v = llrint((double)(qyz * wx[tx]) * kMixedFixedScale);
+        atomicAdd(row + gx[tx], (unsigned long long)v);
+      }
+    }
+  }
+}
+
+// Fixed point -> complex mesh; clears the accumulators for the next call.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mixed_unfix(long long* __restrict__ mesh, cpx<T>* __restrict__ out,
+                                                     int64_t ntot) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  const long long v = mesh[i];
+  mesh[i] = 0;
+  out[i] = cpx<T>{(T)((double)v * (1.0 / kMixedFixedScale)), (T)0};
+}
+
+__device__ __forceinline__ void sincospi_t(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sincospi_t(double x, double* s, double* c) { sincospi(x, s, c); }
+
+// exp(sign 2 pi i a / b) for integers 0 <= a < b
+template <typename T>
+__device__ __forceinline__ cpx<T> unit_root(int a, int b, int sign) {
+  T s, c;
+  sincospi_t((T)(2 * a) / (T)b, &s, &c);
+  return cpx<T>{c, sign > 0 ? s : -s};
+}
+
+// In-place unnormalised DFT of every length-N row along one axis:
+// X[k] = sum_n x[n] exp(sign 2 pi i n k / N).  Row r of component c starts
+// at c * comp_stride + (r / stride) * stride * N + r % stride and its
+// elements are stride apart (stride 1: x rows, Kx: y columns, Kx Ky: z
+// columns).  Grid (rows, components); LDS 2 N complex values.
+// Self-sorting stages: with p points already transformed, butterfly i
+// (0 <= i < N/R) takes x[i + q N/R], q < R, applies the twiddles
+// exp(sign 2 pi i q k / (p R)) with k = i mod p, a length-R DFT, and stores
+// to (i - k) R + k + s p, s < R.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mixed_fft_axis(cpx<T>* __restrict__ data, int N, int64_t stride,
+                                                        int64_t comp_stride, int sign) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cpx<T>* a = reinterpret_cast<cpx<T>*>(smem);
+  cpx<T>* b = a + N;
+  const int64_t r = blockIdx.x;
+  cpx<T>* row = data + (int64_t)blockIdx.y * comp_stride + (r / stride) * stride * N + (r % stride);
+  for (int e = threadIdx.x; e < N; e += blockDim.x) a[e] = row[(int64_t)e * stride];
+  __syncthreads();
+  int p = 1, rem = N;
+  while (rem > 1) {
+    const int R = (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3 : 5;
+    const int nb = N / R;
+    cpx<T> w[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) w[t] = (t < R) ? unit_root<T>(t, R, sign) : cpx<T>{(T)1, (T)0};
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+      const int k = i % p;
+      cpx<T> u[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        if (q < R) {
+          u[q] = a[i + q * nb];
+          if (q > 0 && k > 0) u[q] = cmul(u[q], unit_root<T>((q * k) % (p * R), p * R, sign));
+        }
+      }
+      const int j = (i - k) * R + k;
+#pragma unroll
+      for (int s2 = 0; s2 < 5; ++s2) {
+        if (s2 < R) {
+          cpx<T> v = u[0];
+#pragma unroll
+          for (int q = 1; q < 5; ++q)
+            if (q < R) v = cadd(v, cmul(u[q], w[(q * s2) % R]));
+          b[j + s2 * p] = v;
+        }
+      }
+    }
+    __syncthreads();
+    cpx<T>* t = a;
+    a = b;
+    b = t;
+    p *= R;
+    rem /= R;
+  }
+  for (int e = threadIdx.x; e < N; e += blockDim.x) row[(int64_t)e * stride] = a[e];
+}
+
+// Energy/virial summands and the ik field spectra over the full spectrum:
+//   E^_a(n) = -i k'_a G(n) Q^(n), k'_a = 0 at the Nyquist index of an even K_a;
+//   per block: sum G |Q^|^2 and sum G |Q^|^2 [delta_ab - 2 (1 + k^2/(4 beta^2)) k_a k_b / k^2]
+// in partials[block * 8 + c], c = E, xx, yy, zz, xy, xz, yz.
+// G is the octant table [Kx/2+1][Ky/2+1][Kz/2+1] over |n_a|.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mixed_poisson(const cpx<T>* __restrict__ Qh, cpx<T>* __restrict__ Ef,
+                                                       const double* __restrict__ G, int Kx, int Ky, int Kz,
+                                                       PoissonConsts pc, double* __restrict__ partials) {
+  __shared__ double red[7][256];
+  const int64_t ntot = (int64_t)Kx * Ky * Kz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (i < ntot) {
+    const int ix = (int)(i % Kx);
+    const int iy = (int)((i / Kx) % Ky);
+    const int iz = (int)(i / ((int64_t)Kx * Ky));
+    const int idx[3] = {ix, iy, iz};
+    const int K[3] = {Kx, Ky, Kz};
+    int an[3];
+    double k[3], kd[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int nn = (idx[a] <= K[a] / 2) ? idx[a] : idx[a] - K[a];
+      an[a] = nn < 0 ? -nn : nn;
+      k[a] = pc.two_pi_over_L[a] * (double)nn;
+      kd[a] = ((K[a] & 1) == 0 && idx[a] == K[a] / 2) ? 0.0 : k[a];
+    }
+    const double g = G[((size_t)an[0] * (Ky / 2 + 1) + an[1]) * (Kz / 2 + 1) + an[2]];
+    const cpx<T> qv = Qh[i];
+    const double qx = (double)qv.x, qy = (double)qv.y;
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    if (k2 > 0.0) {
+      const double e = g * (qx * qx + qy * qy);
+      const double c = 2.0 * (1.0 + k2 * pc.inv_4beta2) / k2;
+      acc[0] = e;
+      acc[1] = e * (1.0 - c * k[0] * k[0]);
+      acc[2] = e * (1.0 - c * k[1] * k[1]);
+      acc[3] = e * (1.0 - c * k[2] * k[2]);
+      acc[4] = -e * c * k[0] * k[1];
+      acc[5] = -e * c * k[0] * k[2];
+      acc[6] = -e * c * k[1] * k[2];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T f = (T)(kd[a] * g);  // -i f (x + i y) = f y - i f x
+      Ef[(int64_t)a * ntot + i] = cpx<T>{f * qv.y, -f * qv.x};
+    }
+  }
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) red[c][t] = acc[c];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+#pragma unroll
+      for (int c = 0; c < 7; ++c) red[c][t] += red[c][t + h];
+    }
+    __syncthreads();
+  }
+  if (t < 7) partials[(size_t)blockIdx.x * 8 + t] = red[t][0];
+}
+
+// E = pre * sum of the block partials (and the virial likewise), fixed tree.
+__global__ void __launch_bounds__(256) k_mixed_reduce(const double* __restrict__ partials, int nblk, double pre,
+                                                      double* __restrict__ energy, double* __restrict__ virial) {
+  __shared__ double red[7 * 256];
+  reduce_partials(partials, nblk, pre, energy, virial, red);
+}
+
+// F_ja = (k_e q_j / V) sum_g W(u_j - g) Re E_a(g), caller's order; launch 256
+// threads per block.
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_mixed_gather(const T* __restrict__ ion_pos, const T* __restrict__ ion_q,
+                                                      const T* __restrict__ wc_pos, const T* __restrict__ wc_q,
+                                                      int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
+                                                      int Kx, int Ky, int Kz, const cpx<T>* __restrict__ Ef,
+                                                      T* __restrict__ ion_f, T* __restrict__ wc_f, T fscale,
+                                                      int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t ntot = (int64_t)Kx * Ky * Kz;
+  const T* r = (i < n_ion) ? (ion_pos + 3 * i) : (wc_pos + 3 * (i - n_ion));
+  const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
+  double d[3];
+  const int sx = mixed_stencil<P>((double)r[0], ihx, Kx, d[0]);
+  const int sy = mixed_stencil<P>((double)r[1], ihy, Ky, d[1]);
+  const int sz = mixed_stencil<P>((double)r[2], ihz, Kz, d[2]);
+  T wx[P], wy[P], wz[P];
+  bspline_weights<T, P>((T)d[0], wx);
+  bspline_weights<T, P>((T)d[1], wy);
+  bspline_weights<T, P>((T)d[2], wz);
+  int gx[P];
+#pragma unroll
+  for (int t = 0; t < P; ++t) gx[t] = (sx + t) % Kx;
+  T f0 = 0, f1 = 0, f2 = 0;
+  for (int tz = 0; tz < P; ++tz) {
+    const int gz = (sz + tz) % Kz;
+    for (int ty = 0; ty < P; ++ty) {
+      const int gy = (sy + ty) % Ky;
+      const T wyz = wz[tz] * wy[ty];
+      const int64_t rb = ((int64_t)gz * Ky + gy) * Kx;
+#pragma unroll
+      for (int tx = 0; tx < P; ++tx) {
+        const int64_t e = rb + gx[tx];
+        const T w = wyz * wx[tx];
+        f0 += w * Ef[e].x;
+        f1 += w * Ef[ntot + e].x;
+        f2 += w * Ef[2 * ntot + e].x;
+      }
+    }
+  }
+  const T s = fscale * q;
+  T* out = (i < n_ion) ? (ion_f + 3 * i) : (wc_f + 3 * (i - n_ion));
+  const T v[3] = {s * f0, s * f1, s * f2};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out[a] = accumulate ? out[a] + v[a] : v[a];
+}
+
+}  // namespace dplr

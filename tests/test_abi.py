@@ -60,9 +60,11 @@ def test_default_config_is_valid(lib):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(mesh=[48, 32, 32]), "E_UNSUPPORTED"),
-    (dict(mesh=[8, 32, 32]), "E_UNSUPPORTED"),
+    (dict(mesh=[14, 32, 32]), "E_UNSUPPORTED"),
+    (dict(mesh=[4, 32, 32]), "E_UNSUPPORTED"),
+    (dict(mesh=[48, 32, 32], flags=0x4), "E_UNSUPPORTED"),
     (dict(mesh=[1024, 32, 32]), "E_UNSUPPORTED"),
+    (dict(mesh=[960, 32, 32]), "E_UNSUPPORTED"),
     (dict(mesh=[0, 32, 32]), "E_INVALID"),
     (dict(order=9), "E_UNSUPPORTED"),
     (dict(order=1), "E_UNSUPPORTED"),
@@ -79,6 +81,13 @@ def test_default_config_is_valid(lib):
 def test_invalid_configs_rejected(lib, kw, status):
     st, msg = _validate(lib, _cfg(lib, **kw))
     assert lib.STATUS_NAMES[st] == status and msg
+
+
+@pytest.mark.parametrize("mesh", [[48, 32, 32], [8, 12, 8], [10, 15, 10], [12, 18, 12], [5, 5, 5], [8, 8, 8],
+                                  [512, 375, 500]])
+def test_mixed_radix_meshes_accepted(lib, mesh):
+    # sizes with prime factors 2, 3 and 5 only, each at least the order
+    assert _validate(lib, _cfg(lib, mesh=mesh)) == (lib.OK, "")
 
 
 def test_plan_create_rejects_before_device_work(lib):

@@ -194,3 +194,48 @@ def test_ad_forces_are_the_energy_gradient(p):
             # measured ~1e-9 (FD truncation and rounding); the ik forces of the
             # same energy differ by 3e-4 (p = 5) to 6e-6 (p = 8)
             assert abs(F[j, a] - fd) <= 1e-8 * np.abs(F[j]).max()
+
+
+# ---------------------------------------------------------------------------
+# Meshes that are not powers of two (the paper's precision study uses grids
+# such as 10x15x10): odd sizes have no Nyquist index, even ones drop its
+# derivative.  The exact symmetries and the convergence to Ewald must hold
+# for them as for the power-of-two meshes.
+# ---------------------------------------------------------------------------
+MIXED = (15, 18, 25)
+
+
+def test_mixed_mesh_integer_shift_and_zero_net_force(w64):
+    pos, q = w64.all_pos(), w64.all_q()
+    E, F, W = pppm.pppm(pos, q, w64.box, MIXED, 5, BETA, KE)
+    assert np.linalg.norm(F.sum(0)) / np.abs(F).max() < 1e-12
+    shift = (w64.box / np.array(MIXED)) * np.array([4, -5, 13])
+    E2, F2, W2 = pppm.pppm(np.mod(pos + shift, w64.box), q, w64.box, MIXED, 5, BETA, KE)
+    assert abs(E2 - E) / abs(E) < 1e-13
+    assert np.abs(F2 - F).max() / np.abs(F).max() < 1e-12
+    assert np.abs(W2 - W).max() / abs(E) < 1e-13
+
+
+def test_mixed_mesh_fields_are_real(w64):
+    _, _, _, parts = pppm.pppm(w64.all_pos(), w64.all_q(), w64.box, MIXED, 5, BETA, KE, return_parts=True)
+    for a in range(3):
+        n = np.fft.fftfreq(MIXED[a], 1 / MIXED[a])
+        kd = 2 * math.pi * n / w64.box[a]
+        if MIXED[a] % 2 == 0:
+            kd = np.where(n == -MIXED[a] // 2, 0.0, kd)
+        shape = [1, 1, 1]
+        shape[a] = MIXED[a]
+        Ea = np.fft.ifftn(-1j * kd.reshape(shape) * parts["G"] * parts["Qhat"])
+        assert np.abs(Ea.imag).max() < 1e-12 * np.abs(Ea.real).max()
+
+
+def test_mixed_meshes_converge_to_ewald(w64, ewald64):
+    e0, w0, f0 = ewald64
+    errs = []
+    for K in ((15, 15, 15), (30, 30, 30), (60, 60, 60)):
+        E, F, W = pppm.pppm(w64.all_pos(), w64.all_q(), w64.box, K, 5, BETA, KE)
+        errs.append(pppm.rel_rmse(F, f0))
+    assert errs[0] / errs[1] > 16 and errs[1] / errs[2] > 16
+    E, F, W = pppm.pppm(w64.all_pos(), w64.all_q(), w64.box, (75, 75, 75), 8, BETA, KE)
+    assert abs(E - e0) / abs(e0) < 1e-9
+    assert pppm.rel_rmse(F, f0) < 1e-9
