@@ -31,6 +31,10 @@ With k = 2 pi m the factor phi/(2V) equals the paper's exp(-pi^2 m^2/beta^2) /
 (2 pi V m^2), so as h -> 0 this converges to the direct Ewald sum.
 Everything here uses full (not half) spectra and numpy.fft.
 
+pppm_int32() takes the transforms as the paper's Mixed-Int32 configuration
+does: partial sums over node blocks of each axis, quantised to int32 at a
+scale of 1e7 and summed as integers.
+
 pppm_ad() is the analytic-differentiation variant of the same energy (not in
 the paper, which uses ik; it is the adjacent textbook scheme).  Steps 1-5 and
 9 are shared; the forces are the exact gradient of the step-5 energy:
@@ -250,6 +254,79 @@ def pppm_ad(pos, q, box, K, p: int, beta: float, ke: float, alias: int = 2, G=No
     F = -(ke / V) * q[:, None] * interpolate_grad(pos, box, K, p, phi) / h[None, :]
     if return_parts:
         return E, F, W, dict(Q=Q, Qhat=Qh, G=G, phi=phi)
+    return E, F, W
+
+
+def dft_axis_int32(x, axis: int, nodes: int, scale: float, sign: int):
+    """Unnormalised DFT along one axis as the paper's hardware-offloaded FFT
+    forms it (Optimization section, reduction chains and int32 quantisation):
+    the K points of the axis belong to `nodes` consecutive blocks of K/nodes
+    points; every block forms its partial sum
+        P_b[k] = sum_{n in block b} x[n] exp(sign 2 pi i n k / K),
+    whose real and imaginary parts are scaled by `scale`, rounded to the
+    nearest integer and clamped to the int32 range; the integers are summed
+    over the blocks (exactly) and the sum is divided by `scale`."""
+    x = np.asarray(x, dtype=np.complex128)
+    K = x.shape[axis]
+    if nodes < 1 or K % nodes:
+        raise ValueError("the node count must divide the axis length")
+    seg = K // nodes
+    xm = np.moveaxis(x, axis, -1)
+    k = np.arange(K)
+    lo, hi = -2.0 ** 31, 2.0 ** 31 - 1
+    acc_re = np.zeros(xm.shape, dtype=np.int64)
+    acc_im = np.zeros(xm.shape, dtype=np.int64)
+    for b in range(nodes):
+        n = np.arange(b * seg, (b + 1) * seg)
+        w = np.exp(sign * 2j * math.pi * (np.outer(n, k) % K) / K)
+        P = xm[..., n] @ w
+        acc_re += np.clip(np.rint(P.real * scale), lo, hi).astype(np.int64)
+        acc_im += np.clip(np.rint(P.imag * scale), lo, hi).astype(np.int64)
+    out = (acc_re.astype(np.float64) + 1j * acc_im.astype(np.float64)) / scale
+    return np.moveaxis(out, -1, axis)
+
+
+def pppm_int32(pos, q, box, K, p: int, beta: float, ke: float, nodes, scale: float = 1e7,
+               alias: int = 2, G=None, return_parts: bool = False):
+    """pppm() with the paper's Mixed-Int32 transforms (Evaluation, precision
+    configurations): every 3D transform is taken axis by axis (x, y, z) with
+    dft_axis_int32 and nodes[a] node blocks along axis a.  The charge mesh is
+    transformed in charge units; the field spectra carry k_e / V, so the
+    inverse transforms produce the field itself (eV/A per unit charge), the
+    O(1) values the scaling by `scale` is meant for.  Energy and virial follow
+    from the quantised charge spectrum with the formulas of pppm()."""
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    q = np.asarray(q, dtype=np.float64).reshape(-1)
+    box = np.asarray(box, dtype=np.float64).reshape(3)
+    K = [int(k) for k in K]
+    V = float(np.prod(box))
+    Q = spread(pos, q, box, K, p)
+    Qh = Q.astype(np.complex128)
+    for a in range(3):
+        Qh = dft_axis_int32(Qh, a, int(nodes[a]), scale, -1)
+    if G is None:
+        G = influence(box, K, beta, p, alias)
+    n, k = wavevectors(box, K)
+    kg = np.meshgrid(k[0], k[1], k[2], indexing="ij")
+    s2 = (Qh.conj() * Qh).real
+    E = ke / (2 * V) * float((G * s2).sum())
+    k2 = kg[0] ** 2 + kg[1] ** 2 + kg[2] ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        c = np.where(k2 > 0, 2 * (1 + k2 / (4 * beta * beta)) / k2, 0.0)
+    W = np.empty(6)
+    for i, (a, b) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        W[i] = ke / (2 * V) * float((G * s2 * ((1.0 if a == b else 0.0) - c * kg[a] * kg[b])).sum())
+    F = np.zeros_like(pos)
+    for a in range(3):
+        kd = np.where(n[a] == -K[a] // 2, 0.0, k[a]) if K[a] % 2 == 0 else k[a]
+        shape = [1, 1, 1]
+        shape[a] = K[a]
+        Ea = (ke / V) * (-1j * kd.reshape(shape) * G * Qh)
+        for b in range(3):
+            Ea = dft_axis_int32(Ea, b, int(nodes[b]), scale, +1)
+        F[:, a] = q * interpolate(pos, box, K, p, Ea.real)
+    if return_parts:
+        return E, F, W, dict(Q=Q, Qhat=Qh, G=G)
     return E, F, W
 
 
