@@ -75,7 +75,12 @@ typedef enum { DPLR_LR_FP32 = 0, DPLR_LR_FP64 = 1 } dplr_lr_precision;
 #define DPLR_LR_DIFF_AD    0x4u
 
 typedef struct {
-  int32_t mesh[3];     /* Kx, Ky, Kz: powers of two in [16, 512]                          */
+  int32_t mesh[3];     /* Kx, Ky, Kz, each at most 512 with no prime factor but 2, 3, 5.
+                          Powers of two from 16 up run on the plane/pencil kernels; any
+                          other mesh (e.g. the paper's 8x12x8, 10x15x10 and 12x18x12
+                          precision-study grids, Evaluation section) on the mixed-radix
+                          kernels, which need every size >= order and take no
+                          DPLR_LR_DIFF_AD                                               */
   int32_t order;       /* B-spline assignment order p (points per axis), 2..8             */
   double beta;         /* Gaussian width parameter beta of the E_Gt equation (1/A), > 0  */
   double coulomb_k;    /* Coulomb constant k_e (eV A); E is returned in its units         */
@@ -106,6 +111,22 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
 
 /* Rebind the plan to another stream (hipStream_t). */
 dplr_lr_status dplr_lr_set_stream(dplr_lr_plan p, void* hip_stream);
+
+/* The paper's Mixed-Int32 transforms (Optimization section, int32
+ * quantisation of the FFT reduction chains; Evaluation section, precision
+ * configurations), for mixed-radix plans with every mesh size <= 256.  Each
+ * 1D transform of every 3D transform (x, then y, then z) is formed as the sum
+ * over nodes[a] consecutive blocks of K_a / nodes[a] points of the blocks'
+ * partial DFTs; each partial value (real and imaginary part) is multiplied by
+ * scale, rounded to the nearest integer and clamped to the int32 range, the
+ * integers are added exactly and the sum is divided by scale (the paper uses
+ * scale = 1e7).  The charge spectrum is transformed in charge units and the
+ * field spectra carry k_e / V, so the inverse transforms produce the field
+ * (eV/A per unit charge), values of order one.  nodes (host, 3 ints) must
+ * divide the mesh sizes; scale in (0, 2^31].  nodes = NULL switches the mode
+ * off.  Returns E_UNSUPPORTED on power-of-two plans.  Takes effect from the
+ * next compute; energy and virial come from the quantised charge spectrum. */
+dplr_lr_status dplr_lr_set_fft_int32(dplr_lr_plan p, const int32_t nodes[3], double scale);
 
 /* Set the orthorhombic box (host array of 3 positive lengths, Angstrom) and
  * enqueue the FP64 influence-function table for it: the optimal ik influence

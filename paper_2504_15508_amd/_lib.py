@@ -20,7 +20,7 @@ BUF_SPECTRUM, BUF_INFLUENCE, BUF_FIELD_SPECTRA = 0, 1, 2
 # every symbol include/dplr_lr.h declares
 EXPORTS = [
     "dplr_lr_abi_version", "dplr_lr_config_default", "dplr_lr_config_validate",
-    "dplr_lr_plan_create", "dplr_lr_set_stream", "dplr_lr_set_box",
+    "dplr_lr_plan_create", "dplr_lr_set_stream", "dplr_lr_set_fft_int32", "dplr_lr_set_box",
     "dplr_lr_compute_energy_forces_virial", "dplr_lr_scale_grad", "dplr_lr_plan_destroy",
     "dplr_lr_last_error", "dplr_lr_workspace_bytes", "dplr_lr_debug_copy", "dplr_lr_debug_size",
     "dplr_lr_profile_enable", "dplr_lr_profile_read", "dplr_lr_profile_stage_name",
@@ -80,6 +80,7 @@ def load():
         "dplr_lr_config_validate": ([cfgp, ctypes.c_char_p, i64], ctypes.c_int),
         "dplr_lr_plan_create": ([cfgp, p, ctypes.POINTER(p)], ctypes.c_int),
         "dplr_lr_set_stream": ([p, p], ctypes.c_int),
+        "dplr_lr_set_fft_int32": ([p, ctypes.POINTER(i32), d], ctypes.c_int),
         "dplr_lr_set_box": ([p, ctypes.POINTER(d)], ctypes.c_int),
         "dplr_lr_compute_energy_forces_virial": ([p, i64, p, p, i64, p, p, p, p, p, p], ctypes.c_int),
         "dplr_lr_scale_grad": ([p, p, i64, p, p, i64, p, p], ctypes.c_int),

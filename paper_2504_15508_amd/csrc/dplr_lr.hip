@@ -69,6 +69,7 @@ constexpr int kMinMesh = 16;
 constexpr int kMaxMesh = 512;
 constexpr int kMaxOrder = 8;
 constexpr int kMinOrder = 2;
+constexpr int kMaxQ32Mesh = 256;  // int32-quantised transforms are direct sums, O(K) per output
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -153,6 +154,8 @@ struct dplr_lr_plan_s {
   void* mspec = nullptr;      // ... its full complex spectrum
   void* mfield = nullptr;     // ... three full field spectra, transformed back in place
   int mblk = 0;               // ... blocks (and partials) of the ik multiply
+  int q32_nodes[3] = {0, 0, 0};  // int32-quantised transforms: node blocks per axis (0: off)
+  double q32_scale = 0.0;
   int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_ifftx = 256, thr_ixy = 256;
   // device workspace
   int* bin_count = nullptr;
@@ -580,6 +583,18 @@ void launch_mixed_fft(dplr_lr_plan p, cpx<T>* data, int ncomp, int sign) {
   }
 }
 
+template <typename T>
+void launch_mixed_dft_q32(dplr_lr_plan p, cpx<T>* data, int ncomp, int sign) {
+  const int K[3] = {p->geo.K[0], p->geo.K[1], p->geo.K[2]};
+  const int64_t ntot = (int64_t)K[0] * K[1] * K[2];
+  const int64_t stride[3] = {1, K[0], (int64_t)K[0] * K[1]};
+  for (int a = 0; a < 3; ++a) {
+    const int64_t rows = ntot / K[a];
+    hipLaunchKernelGGL(k_mixed_dft_q32<T>, dim3((unsigned)rows, (unsigned)ncomp), dim3(64), sizeof(cpx<T>) * K[a],
+                       p->stream, data, K[a], stride[a], ntot, sign, p->q32_nodes[a], p->q32_scale);
+  }
+}
+
 template <typename T, int P>
 dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, const void* ion_q, int64_t n_wc,
                             const void* wc_pos, const void* wc_q, void* ion_force, void* wc_force, double* energy,
@@ -591,6 +606,9 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
   const double ih[3] = {g.K[0] / p->box[0], g.K[1] / p->box[1], g.K[2] / p->box[2]};
   cpx<T>* spec = reinterpret_cast<cpx<T>*>(p->mspec);
   cpx<T>* field = reinterpret_cast<cpx<T>*>(p->mfield);
+  // quantised transforms: the field spectra carry k_e / V so that the inverse
+  // transforms work on the field itself (O(1) values)
+  const bool q32 = p->q32_nodes[0] > 0;
   const unsigned nbp = (unsigned)((n + 255) / 256);
   if (n > 0) {
     ProfScope ps(p, 11);
@@ -601,7 +619,8 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
   {
     ProfScope ps(p, 12);
     hipLaunchKernelGGL(k_mixed_unfix<T>, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, p->mmesh, spec, ntot);
-    launch_mixed_fft<T>(p, spec, 1, -1);
+    if (q32) launch_mixed_dft_q32<T>(p, spec, 1, -1);
+    else launch_mixed_fft<T>(p, spec, 1, -1);
   }
   PoissonConsts pc;
   for (int a = 0; a < 3; ++a) pc.two_pi_over_L[a] = 2.0 * M_PI / p->box[a];
@@ -611,19 +630,20 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
   {
     ProfScope ps(p, 13);
     hipLaunchKernelGGL(k_mixed_poisson<T>, dim3((unsigned)p->mblk), dim3(256), 0, s, spec, field, p->G, g.K[0],
-                       g.K[1], g.K[2], pc, p->partials);
+                       g.K[1], g.K[2], pc, q32 ? p->cfg.coulomb_k / V : 1.0, p->partials);
     hipLaunchKernelGGL(k_mixed_reduce, dim3(1), dim3(256), 0, s, (const double*)p->partials, p->mblk,
                        p->cfg.coulomb_k / (2.0 * V), energy, want_virial ? virial : (double*)nullptr);
   }
   if (n > 0) {
     {
       ProfScope ps(p, 14);
-      launch_mixed_fft<T>(p, field, 3, +1);
+      if (q32) launch_mixed_dft_q32<T>(p, field, 3, +1);
+      else launch_mixed_fft<T>(p, field, 3, +1);
     }
     ProfScope ps(p, 15);
     hipLaunchKernelGGL((k_mixed_gather<T, P>), dim3(nbp), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
                        (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], g.K[0], g.K[1], g.K[2],
-                       (const cpx<T>*)field, (T*)ion_force, (T*)wc_force, (T)(p->cfg.coulomb_k / V),
+                       (const cpx<T>*)field, (T*)ion_force, (T*)wc_force, q32 ? (T)1 : (T)(p->cfg.coulomb_k / V),
                        (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0);
   }
   hipError_t e = hipGetLastError();
@@ -791,6 +811,24 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
   }
   if (p->fp64) set_lds_attrs<double>(p); else set_lds_attrs<float>(p);
   *out = p;
+  return DPLR_LR_OK;
+}
+
+dplr_lr_status dplr_lr_set_fft_int32(dplr_lr_plan p, const int32_t nodes[3], double scale) {
+  if (!p) return fail(nullptr, DPLR_LR_E_INVALID, "plan is NULL");
+  if (!nodes) {
+    for (int a = 0; a < 3; ++a) p->q32_nodes[a] = 0;
+    p->q32_scale = 0.0;
+    return DPLR_LR_OK;
+  }
+  if (!p->mixed) return fail(p, DPLR_LR_E_UNSUPPORTED, "int32 transforms are available on mixed-radix plans only");
+  if (!(scale > 0.0) || !(scale <= 2147483648.0)) return fail(p, DPLR_LR_E_INVALID, "scale must be in (0, 2^31]");
+  for (int a = 0; a < 3; ++a) {
+    if (nodes[a] < 1 || p->geo.K[a] % nodes[a]) return fail(p, DPLR_LR_E_INVALID, "node counts must divide the mesh sizes");
+    if (p->geo.K[a] > kMaxQ32Mesh) return fail(p, DPLR_LR_E_UNSUPPORTED, "int32 transforms take mesh sizes up to 256");
+  }
+  for (int a = 0; a < 3; ++a) p->q32_nodes[a] = nodes[a];
+  p->q32_scale = scale;
   return DPLR_LR_OK;
 }
 

@@ -164,15 +164,51 @@ __global__ void __launch_bounds__(256) k_mixed_fft_axis(cpx<T>* __restrict__ dat
   for (int e = threadIdx.x; e < N; e += blockDim.x) row[(int64_t)e * stride] = a[e];
 }
 
+// The same row transform taken as the paper's hardware-offloaded FFT forms it
+// in its Mixed-Int32 configuration (Optimization section, int32 quantisation of
+// the reduction chains): the N points of a row belong to `nodes` consecutive
+// blocks of N / nodes points; each block's partial sum
+//   P_b[k] = sum_{n in block b} x[n] exp(sign 2 pi i n k / N)
+// is scaled by `scale`, rounded to the nearest integer and clamped to the
+// int32 range (real and imaginary parts apart), the integers are summed over
+// the blocks exactly and the sum is divided by `scale`.  Direct sums, O(N)
+// per output.  Grid (rows, components); LDS N complex values.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mixed_dft_q32(cpx<T>* __restrict__ data, int N, int64_t stride,
+                                                       int64_t comp_stride, int sign, int nodes, double scale) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cpx<T>* a = reinterpret_cast<cpx<T>*>(smem);
+  const int64_t r = blockIdx.x;
+  cpx<T>* row = data + (int64_t)blockIdx.y * comp_stride + (r / stride) * stride * N + (r % stride);
+  for (int e = threadIdx.x; e < N; e += blockDim.x) a[e] = row[(int64_t)e * stride];
+  __syncthreads();
+  const int seg = N / nodes;
+  const T sc = (T)scale;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    long long acc_re = 0, acc_im = 0;
+    for (int bk = 0; bk < nodes; ++bk) {
+      cpx<T> s = {(T)0, (T)0};
+      for (int n = bk * seg; n < (bk + 1) * seg; ++n)
+        s = cadd(s, cmul(a[n], unit_root<T>((int)(((int64_t)n * k) % N), N, sign)));
+      // the product and its rounding in the plan's precision, the clamp in FP64
+      acc_re += (long long)fmin(fmax((double)rint(s.x * sc), -2147483648.0), 2147483647.0);
+      acc_im += (long long)fmin(fmax((double)rint(s.y * sc), -2147483648.0), 2147483647.0);
+    }
+    row[(int64_t)k * stride] = cpx<T>{(T)((double)acc_re / scale), (T)((double)acc_im / scale)};
+  }
+}
+
 // Energy/virial summands and the ik field spectra over the full spectrum:
-//   E^_a(n) = -i k'_a G(n) Q^(n), k'_a = 0 at the Nyquist index of an even K_a;
+//   E^_a(n) = -i fmul k'_a G(n) Q^(n), k'_a = 0 at the Nyquist index of an even K_a
+//   (fmul = 1, or k_e / V when the inverse transforms are quantised);
 //   per block: sum G |Q^|^2 and sum G |Q^|^2 [delta_ab - 2 (1 + k^2/(4 beta^2)) k_a k_b / k^2]
 // in partials[block * 8 + c], c = E, xx, yy, zz, xy, xz, yz.
 // G is the octant table [Kx/2+1][Ky/2+1][Kz/2+1] over |n_a|.
 template <typename T>
 __global__ void __launch_bounds__(256) k_mixed_poisson(const cpx<T>* __restrict__ Qh, cpx<T>* __restrict__ Ef,
                                                        const double* __restrict__ G, int Kx, int Ky, int Kz,
-                                                       PoissonConsts pc, double* __restrict__ partials) {
+                                                       PoissonConsts pc, double fmul,
+                                                       double* __restrict__ partials) {
   __shared__ double red[7][256];
   const int64_t ntot = (int64_t)Kx * Ky * Kz;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,7 +245,7 @@ __global__ void __launch_bounds__(256) k_mixed_poisson(const cpx<T>* __restrict_
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const T f = (T)(kd[a] * g);  // -i f (x + i y) = f y - i f x
+      const T f = (T)(fmul * (kd[a] * g));  // -i f (x + i y) = f y - i f x
       Ef[(int64_t)a * ntot + i] = cpx<T>{f * qv.y, -f * qv.x};
     }
   }

@@ -60,6 +60,17 @@ class Plan:
         self.box = None
         self.last_virial = None
 
+    def set_fft_int32(self, nodes=None, scale: float = 1e7):
+        """The paper's Mixed-Int32 transforms on a mixed-radix plan: node-block
+        partial DFTs quantised to int32 at `scale` (see include/dplr_lr.h);
+        nodes=None switches them off."""
+        lib = _lib.load()
+        if nodes is None:
+            self._check(lib.dplr_lr_set_fft_int32(self._h, None, 0.0))
+            return
+        arr = (ctypes.c_int32 * 3)(*[int(v) for v in nodes])
+        self._check(lib.dplr_lr_set_fft_int32(self._h, arr, float(scale)))
+
     # -- plumbing ---------------------------------------------------------
     def _bind_stream(self):
         s = torch.cuda.current_stream(self.device).cuda_stream

@@ -120,3 +120,68 @@ def test_mixed_mesh_rejects_ad_and_bad_sizes(torch_dev):
         dl.Plan((14, 18, 12), order=5, precision="fp64", capacity=10)
     with pytest.raises(Exception, match="order"):
         dl.Plan((4, 18, 12), order=5, precision="fp64", capacity=10)
+
+
+# ---------------------------------------------------------------------------
+# The paper's Mixed-Int32 transforms (node-block partial DFTs quantised to
+# int32 at 1e7) against the oracle's pppm_int32.  Exact ties are frequent:
+# after the first quantised axis every value is a multiple of the quantum,
+# and twiddles such as cos(60 deg) = 1/2 put partial sums on half-quanta,
+# where the last bit of a twiddle (sincospi on the GPU, exp in NumPy) decides
+# the rounding.  Both roundings are valid, and each moves one partial value by
+# one quantum (1e-7), so the FP64 bars are one quantum's scale: 1e-7 in the
+# forces and 1e-8 in energy and virial, and a quarter of the int32 effect
+# itself (int32 against exact transforms).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mesh", PAPER_GRIDS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_int32_transforms_match_oracle(torch_dev, mesh, precision):
+    import paper_2504_15508_amd as dl
+    torch = torch_dev
+    s = small_water()
+    ref = s.rounded(np.float32) if precision == "fp32" else s
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    plan = dl.Plan(mesh, order=5, beta=BETA, coulomb_k=KE, precision=precision, capacity=s.n)
+    plan.set_box(s.box)
+    plan.set_fft_int32((2, 3, 2), 1e7)
+    E, fi, fw, W = plan.compute(t(ref.ion_pos), t(ref.ion_q), t(ref.wc_pos), t(ref.wc_q))
+    torch.cuda.synchronize()
+    F = np.concatenate([fi.double().cpu().numpy(), fw.double().cpu().numpy()])
+    E0, F0, W0 = pppm.pppm_int32(ref.all_pos(), ref.all_q(), ref.box, mesh, 5, BETA, KE, (2, 3, 2), 1e7)
+    E1, F1, _ = pppm.pppm(ref.all_pos(), ref.all_q(), ref.box, mesh, 5, BETA, KE)
+    dE, dF = abs(float(E) - E0) / abs(E0), rel(F, F0)
+    dW = np.abs(W.cpu().numpy() - W0).max() / abs(E0)
+    print(f"int32 {mesh} {precision}: dE={dE:.2e} dF={dF:.2e} dW={dW:.2e}  "
+          f"(int32 vs exact transforms: {rel(F0, F1):.2e})", flush=True)
+    if precision == "fp64":
+        assert dF <= 1e-7 and dE <= 1e-8 and dW <= 1e-8
+        assert dF <= 0.25 * rel(F0, F1)
+    else:
+        assert dF <= FP32_TOL_F and dE <= FP32_TOL_E and dW <= FP32_TOL_E
+
+
+def test_int32_mode_switches_and_rejections(torch_dev):
+    import paper_2504_15508_amd as dl
+    torch = torch_dev
+    s = small_water()
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    plan = dl.Plan((10, 15, 10), order=5, beta=BETA, coulomb_k=KE, precision="fp64", capacity=s.n)
+    plan.set_box(s.box)
+    args = (t(s.ion_pos), t(s.ion_q), t(s.wc_pos), t(s.wc_q))
+    _, fa, _, _ = plan.compute(*args)
+    fa = fa.clone()
+    plan.set_fft_int32((2, 3, 2))
+    _, fb, _, _ = plan.compute(*args)
+    fb = fb.clone()
+    plan.set_fft_int32(None)
+    _, fc, _, _ = plan.compute(*args)
+    torch.cuda.synchronize()
+    assert torch.equal(fa, fc) and not torch.equal(fa, fb)
+    with pytest.raises(Exception, match="divide"):
+        plan.set_fft_int32((3, 3, 2))
+    with pytest.raises(Exception, match="scale"):
+        plan.set_fft_int32((2, 3, 2), 0.0)
+    p2 = dl.Plan(32, order=5, precision="fp64", capacity=10)
+    with pytest.raises(Exception, match="mixed-radix"):
+        p2.set_fft_int32((2, 2, 2))
