@@ -257,6 +257,56 @@ def overlap_leg(plan, step, W, K, n_atoms, energy, dev):
                                    f"{n_atoms} atoms"}
 
 
+def mixed_leg(args, make_plan, step, timed_graph, timed_eager, s0, qi, qw, w, dev):
+    """The mixed-radix kernels: the same 216,576 + 72,192 charges on a 120^3
+    mesh (h = 1.078 A, next to the 128^3 of the headline), and the paper's
+    12x18x12 precision-study grid (128 waters, 16 A) with exact and with
+    int32-quantised transforms."""
+    import numpy as np
+    import torch
+    import systems
+    import paper_2504_15508_amd as dl
+
+    out = {}
+    gpath = os.path.join(ROOT, "tests", "golden", f"ewald_{w.name}.json")
+    p = make_plan(args.order, mesh=(120, 120, 120))
+    if os.path.exists(gpath):
+        gold = json.load(open(gpath))
+        idx = np.array(gold["sample_index"])
+        fref = np.array(gold["sample_force"])
+        r0 = torch.tensor(s0.ion_pos, dtype=torch.float32, device=dev)
+        w0 = torch.tensor(s0.wc_pos, dtype=torch.float32, device=dev)
+        E, a, b, _ = p.compute(r0, qi, w0, qw)
+        F = torch.cat([a, b]).double().cpu().numpy()[idx]
+        out["mixed120_force_rmse_vs_ewald"] = float(np.linalg.norm(F - fref) / np.linalg.norm(fref))
+    if args.eager_only:
+        out["mixed120_ms_per_step"] = 1e3 * timed_eager(p, False)[0]
+    else:
+        out["mixed120_ms_per_step"] = 1e3 * timed_graph(lambda t: step(p, t))
+        _, prof = timed_eager(p, True)
+        out["mixed120_kernels_us"] = {k: round(1e3 * v[0] / max(v[1], 1), 2) for k, v in prof.items() if v[1]}
+    p.close()
+    # the paper's grid: launch-bound; eager calls on one frame
+    sm = systems.water_box(128, 16.0, seed=20261128)
+    t = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
+    args_sm = (t(sm.ion_pos), t(sm.ion_q), t(sm.wc_pos), t(sm.wc_q))
+    for tag, nodes in (("grid12x18x12", None), ("grid12x18x12_int32", (2, 3, 2))):
+        ps = dl.Plan((12, 18, 12), order=5, beta=w.beta, coulomb_k=w.coulomb_k, precision="fp32", capacity=sm.n)
+        ps.set_box(sm.box)
+        if nodes:
+            ps.set_fft_int32(nodes, 1e7)
+        for _ in range(5):
+            ps.compute(*args_sm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(50):
+            ps.compute(*args_sm)
+        torch.cuda.synchronize()
+        out[f"{tag}_ms_per_call"] = 1e3 * (time.perf_counter() - t0) / 50
+        ps.close()
+    return out
+
+
 def learned_leg(args, w, s0, ion_d, wc_d, qi, qw, dev, timed_graph_fn, plain_ms, gold):
     """Learned coarse form: train the correction on spacing-matched boxes
     (1,128 waters in 32.325 A, meshes 16^3 / 32^3 = the spacings of 64^3 /
@@ -480,6 +530,11 @@ def main():
                         p.close()
         except Exception as e:  # extras never hide the headline measurement
             extras["extras_error"] = repr(e)
+    if not args.no_extras:
+        try:
+            extras.update(mixed_leg(args, make_plan, step, timed_graph, timed_eager, s0, qi, qw, w, dev))
+        except Exception as e:
+            extras["mixed_error"] = repr(e)
     if not args.no_extras and not args.eager_only:
         try:
             extras.update(overlap_leg(plan, step, W, K, s0.n_ion, energy, dev))
