@@ -609,7 +609,9 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
   // quantised transforms: the field spectra carry k_e / V so that the inverse
   // transforms work on the field itself (O(1) values)
   const bool q32 = p->q32_nodes[0] > 0;
-  const unsigned nbp = (unsigned)((n + 255) / 256);
+  // spread: one thread per (particle, stencil plane); gather: 256 / P particles per block
+  const unsigned nbp = (unsigned)((n * P + 255) / 256);
+  const unsigned nbg = (unsigned)((n + 256 / P - 1) / (256 / P));
   if (n > 0) {
     ProfScope ps(p, 11);
     hipLaunchKernelGGL((k_mixed_spread<T, P>), dim3(nbp), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
@@ -641,7 +643,7 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
       else launch_mixed_fft<T>(p, field, 3, +1);
     }
     ProfScope ps(p, 15);
-    hipLaunchKernelGGL((k_mixed_gather<T, P>), dim3(nbp), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
+    hipLaunchKernelGGL((k_mixed_gather<T, P>), dim3(nbg), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
                        (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], g.K[0], g.K[1], g.K[2],
                        (const cpx<T>*)field, (T*)ion_force, (T*)wc_force, q32 ? (T)1 : (T)(p->cfg.coulomb_k / V),
                        (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0);

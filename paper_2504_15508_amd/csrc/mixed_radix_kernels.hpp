@@ -47,14 +47,17 @@ __device__ __forceinline__ int mixed_stencil(double r, double invh, int K, doubl
   return s;
 }
 
+// One thread per (particle, stencil plane tz): P^2 atomics each.
 template <typename T, int P>
 __global__ void __launch_bounds__(256) k_mixed_spread(const T* __restrict__ ion_pos, const T* __restrict__ ion_q,
                                                       const T* __restrict__ wc_pos, const T* __restrict__ wc_q,
                                                       int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
                                                       int Kx, int Ky, int Kz,
                                                       unsigned long long* __restrict__ mesh) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= n * P) return;
+  const int64_t i = it / P;
+  const int tz = (int)(it - i * P);
   const T* r = (i < n_ion) ? (ion_pos + 3 * i) : (wc_pos + 3 * (i - n_ion));
   const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
   double d[3];
@@ -68,18 +71,19 @@ __global__ void __launch_bounds__(256) k_mixed_spread(const T* __restrict__ ion_
   int gx[P];
 #pragma unroll
   for (int t = 0; t < P; ++t) gx[t] = (sx + t) % Kx;
-  for (int tz = 0; tz < P; ++tz) {
-    const int gz = (sz + tz) % Kz;
-    const T qz = q * wz[tz];
-    for (int ty = 0; ty < P; ++ty) {
-      const int gy = (sy + ty) % Ky;
-      const T qyz = qz * wy[ty];
-      unsigned long long* row = mesh + ((size_t)gz * Ky + gy) * Kx;
+  T wzt = wz[0];
 #pragma unroll
-      for (int tx = 0; tx < P; ++tx) {
-        const long long v = llrint((double)(qyz * wx[tx]) * kMixedFixedScale);
-        atomicAdd(row + gx[tx], (unsigned long long)v);
-      }
+  for (int t = 1; t < P; ++t) wzt = (tz == t) ? wz[t] : wzt;
+  const int gz = (sz + tz) % Kz;
+  const T qz = q * wzt;
+  for (int ty = 0; ty < P; ++ty) {
+    const int gy = (sy + ty) % Ky;
+    const T qyz = qz * wy[ty];
+    unsigned long long* row = mesh + ((size_t)gz * Ky + gy) * Kx;
+#pragma unroll
+    for (int tx = 0; tx < P; ++tx) {
+      const long long v = llrint((double)(qyz * wx[tx]) * kMixedFixedScale);
+      atomicAdd(row + gx[tx], (unsigned long long)v);
     }
   }
 }
@@ -115,6 +119,32 @@ __device__ __forceinline__ cpx<T> unit_root(int a, int b, int sign) {
 // (0 <= i < N/R) takes x[i + q N/R], q < R, applies the twiddles
 // exp(sign 2 pi i q k / (p R)) with k = i mod p, a length-R DFT, and stores
 // to (i - k) R + k + s p, s < R.
+template <typename T, int R>
+__device__ __forceinline__ void stockham_stage(const cpx<T>* __restrict__ a, cpx<T>* __restrict__ b, int N, int p,
+                                               int sign) {
+  const int nb = N / R;
+  cpx<T> w[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) w[t] = unit_root<T>(t, R, sign);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    const int k = i % p;
+    cpx<T> u[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      u[q] = a[i + q * nb];
+      if (q > 0 && k > 0) u[q] = cmul(u[q], unit_root<T>((q * k) % (p * R), p * R, sign));
+    }
+    const int j = (i - k) * R + k;
+#pragma unroll
+    for (int s2 = 0; s2 < R; ++s2) {
+      cpx<T> v = u[0];
+#pragma unroll
+      for (int q = 1; q < R; ++q) v = cadd(v, cmul(u[q], w[(q * s2) % R]));
+      b[j + s2 * p] = v;
+    }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_mixed_fft_axis(cpx<T>* __restrict__ data, int N, int64_t stride,
                                                         int64_t comp_stride, int sign) {
@@ -128,31 +158,11 @@ __global__ void __launch_bounds__(256) k_mixed_fft_axis(cpx<T>* __restrict__ dat
   int p = 1, rem = N;
   while (rem > 1) {
     const int R = (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3 : 5;
-    const int nb = N / R;
-    cpx<T> w[5];
-#pragma unroll
-    for (int t = 0; t < 5; ++t) w[t] = (t < R) ? unit_root<T>(t, R, sign) : cpx<T>{(T)1, (T)0};
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-      const int k = i % p;
-      cpx<T> u[5];
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        if (q < R) {
-          u[q] = a[i + q * nb];
-          if (q > 0 && k > 0) u[q] = cmul(u[q], unit_root<T>((q * k) % (p * R), p * R, sign));
-        }
-      }
-      const int j = (i - k) * R + k;
-#pragma unroll
-      for (int s2 = 0; s2 < 5; ++s2) {
-        if (s2 < R) {
-          cpx<T> v = u[0];
-#pragma unroll
-          for (int q = 1; q < 5; ++q)
-            if (q < R) v = cadd(v, cmul(u[q], w[(q * s2) % R]));
-          b[j + s2 * p] = v;
-        }
-      }
+    switch (R) {
+      case 4: stockham_stage<T, 4>(a, b, N, p, sign); break;
+      case 2: stockham_stage<T, 2>(a, b, N, p, sign); break;
+      case 3: stockham_stage<T, 3>(a, b, N, p, sign); break;
+      default: stockham_stage<T, 5>(a, b, N, p, sign); break;
     }
     __syncthreads();
     cpx<T>* t = a;
@@ -270,8 +280,9 @@ __global__ void __launch_bounds__(256) k_mixed_reduce(const double* __restrict__
   reduce_partials(partials, nblk, pre, energy, virial, red);
 }
 
-// F_ja = (k_e q_j / V) sum_g W(u_j - g) Re E_a(g), caller's order; launch 256
-// threads per block.
+// F_ja = (k_e q_j / V) sum_g W(u_j - g) Re E_a(g), caller's order.  Block of
+// 256 threads: 256 / P particles, one thread per (particle, stencil plane tz);
+// the P plane sums of a particle are added in tz order (deterministic).
 template <typename T, int P>
 __global__ void __launch_bounds__(256) k_mixed_gather(const T* __restrict__ ion_pos, const T* __restrict__ ion_q,
                                                       const T* __restrict__ wc_pos, const T* __restrict__ wc_q,
@@ -279,11 +290,15 @@ __global__ void __launch_bounds__(256) k_mixed_gather(const T* __restrict__ ion_
                                                       int Kx, int Ky, int Kz, const cpx<T>* __restrict__ Ef,
                                                       T* __restrict__ ion_f, T* __restrict__ wc_f, T fscale,
                                                       int accumulate) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  __shared__ T part[256][3];
+  constexpr int PPB = 256 / P;
+  const int jl = threadIdx.x / P, tz = threadIdx.x % P;
+  const int64_t i = (int64_t)blockIdx.x * PPB + jl;
+  const bool on = jl < PPB && i < n;
+  T f0 = 0, f1 = 0, f2 = 0;
+  if (on) {
   const int64_t ntot = (int64_t)Kx * Ky * Kz;
   const T* r = (i < n_ion) ? (ion_pos + 3 * i) : (wc_pos + 3 * (i - n_ion));
-  const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
   double d[3];
   const int sx = mixed_stencil<P>((double)r[0], ihx, Kx, d[0]);
   const int sy = mixed_stencil<P>((double)r[1], ihy, Ky, d[1]);
@@ -295,26 +310,41 @@ __global__ void __launch_bounds__(256) k_mixed_gather(const T* __restrict__ ion_
   int gx[P];
 #pragma unroll
   for (int t = 0; t < P; ++t) gx[t] = (sx + t) % Kx;
-  T f0 = 0, f1 = 0, f2 = 0;
-  for (int tz = 0; tz < P; ++tz) {
-    const int gz = (sz + tz) % Kz;
-    for (int ty = 0; ty < P; ++ty) {
-      const int gy = (sy + ty) % Ky;
-      const T wyz = wz[tz] * wy[ty];
-      const int64_t rb = ((int64_t)gz * Ky + gy) * Kx;
+  T wzt = wz[0];
 #pragma unroll
-      for (int tx = 0; tx < P; ++tx) {
-        const int64_t e = rb + gx[tx];
-        const T w = wyz * wx[tx];
-        f0 += w * Ef[e].x;
-        f1 += w * Ef[ntot + e].x;
-        f2 += w * Ef[2 * ntot + e].x;
-      }
+  for (int t = 1; t < P; ++t) wzt = (tz == t) ? wz[t] : wzt;
+  const int gz = (sz + tz) % Kz;
+#pragma unroll
+  for (int ty = 0; ty < P; ++ty) {
+    const int gy = (sy + ty) % Ky;
+    const T wyz = wzt * wy[ty];
+    const int64_t rb = ((int64_t)gz * Ky + gy) * Kx;
+#pragma unroll
+    for (int tx = 0; tx < P; ++tx) {
+      const int64_t e = rb + gx[tx];
+      const T w = wyz * wx[tx];
+      f0 += w * Ef[e].x;
+      f1 += w * Ef[ntot + e].x;
+      f2 += w * Ef[2 * ntot + e].x;
     }
   }
+  }
+  part[threadIdx.x][0] = f0;
+  part[threadIdx.x][1] = f1;
+  part[threadIdx.x][2] = f2;
+  __syncthreads();
+  if (!on || tz != 0) return;
+  T g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    g0 += part[threadIdx.x + t][0];
+    g1 += part[threadIdx.x + t][1];
+    g2 += part[threadIdx.x + t][2];
+  }
+  const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
   const T s = fscale * q;
   T* out = (i < n_ion) ? (ion_f + 3 * i) : (wc_f + 3 * (i - n_ion));
-  const T v[3] = {s * f0, s * f1, s * f2};
+  const T v[3] = {s * g0, s * g1, s * g2};
 #pragma unroll
   for (int a = 0; a < 3; ++a) out[a] = accumulate ? out[a] + v[a] : v[a];
 }
