@@ -185,3 +185,11 @@ def test_int32_mode_switches_and_rejections(torch_dev):
     p2 = dl.Plan(32, order=5, precision="fp64", capacity=10)
     with pytest.raises(Exception, match="mixed-radix"):
         p2.set_fft_int32((2, 2, 2))
+
+
+def test_full_size_mixed_mesh_fp32(torch_dev):
+    # the benchmark's 216,576 atoms + 72,192 WCs on a 120^3 mesh (the bench
+    # leg's launch), element-wise against the oracle at the same mesh
+    w = systems.workload(3)
+    s = w.system()
+    check_vs_pppm(torch_dev, s, (120, 120, 120), 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
