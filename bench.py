@@ -303,6 +303,22 @@ def mixed_leg(args, make_plan, step, timed_graph, timed_eager, s0, qi, qw, w, de
             ps.compute(*args_sm)
         torch.cuda.synchronize()
         out[f"{tag}_ms_per_call"] = 1e3 * (time.perf_counter() - t0) / 50
+        if not args.eager_only:
+            # 50 calls captured in one graph: the launch overhead removed
+            stream = torch.cuda.Stream(device=dev)
+            with torch.cuda.stream(stream):
+                ps.compute(*args_sm)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                for _ in range(50):
+                    ps.compute(*args_sm)
+            g.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.replay()
+            torch.cuda.synchronize()
+            out[f"{tag}_graph_ms_per_call"] = 1e3 * (time.perf_counter() - t0) / 50
         ps.close()
     return out
 
