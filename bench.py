@@ -286,7 +286,7 @@ def mixed_leg(args, make_plan, step, timed_graph, timed_eager, s0, qi, qw, w, de
         _, prof = timed_eager(p, True)
         out["mixed120_kernels_us"] = {k: round(1e3 * v[0] / max(v[1], 1), 2) for k, v in prof.items() if v[1]}
     p.close()
-    # the paper's grid: launch-bound; eager calls on one frame
+    # the paper's grid: eleven small kernels; eager calls on one frame
     sm = systems.water_box(128, 16.0, seed=20261128)
     t = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
     args_sm = (t(sm.ion_pos), t(sm.ion_q), t(sm.wc_pos), t(sm.wc_q))
