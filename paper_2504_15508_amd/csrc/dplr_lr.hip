@@ -69,8 +69,7 @@ constexpr int kMinMesh = 16;
 constexpr int kMaxMesh = 512;
 constexpr int kMaxOrder = 8;
 constexpr int kMinOrder = 2;
-constexpr int kMaxQ32Mesh = 256;
-constexpr int64_t kSmallMaxParticles = 8192;  // capacity limit of the one-workgroup mixed-radix step  // int32-quantised transforms are direct sums, O(K) per output
+constexpr int kMaxQ32Mesh = 256;  // int32-quantised transforms are direct sums, O(K) per output
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -155,8 +154,6 @@ struct dplr_lr_plan_s {
   void* mspec = nullptr;      // ... its full complex spectrum
   void* mfield = nullptr;     // ... three full field spectra, transformed back in place
   int mblk = 0;               // ... blocks (and partials) of the ik multiply
-  bool msmall = false;        // ... whole step in one workgroup (mesh in LDS)
-  size_t lds_small = 0;
   int q32_nodes[3] = {0, 0, 0};  // int32-quantised transforms: node blocks per axis (0: off)
   double q32_scale = 0.0;
   int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_ifftx = 256, thr_ixy = 256;
@@ -185,8 +182,8 @@ struct dplr_lr_plan_s {
   struct ProfRec { int stage; hipEvent_t a, b; };
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> prof_pool;
-  double prof_ms[20] = {0};
-  int64_t prof_calls[20] = {0};
+  double prof_ms[16] = {0};
+  int64_t prof_calls[16] = {0};
 };
 
 namespace {
@@ -194,9 +191,9 @@ namespace {
 const char* const kStageNames[] = {"bin_count", "bin_scan", "bin_scatter", "spread_fftx", "ffty_fwd",
                                    "fftz_poisson", "ffty_inv_reduce", "ifftx", "gather", "spread_xy",
                                    "ifft_xy_reduce", "mixed_spread", "mixed_fft_fwd", "mixed_poisson",
-                                   "mixed_fft_inv", "mixed_gather", "mixed_fused"};
-constexpr int kNumStages = 17;
-static_assert(kNumStages <= 20, "profile slots");
+                                   "mixed_fft_inv", "mixed_gather"};
+constexpr int kNumStages = 16;
+static_assert(kNumStages <= 16, "profile slots");
 
 hipEvent_t prof_event(dplr_lr_plan p) {
   if (!p->prof_pool.empty()) {
@@ -606,32 +603,6 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
   hipStream_t s = p->stream;
   const int64_t n = n_ion + n_wc;
   const int64_t ntot = (int64_t)g.K[0] * g.K[1] * g.K[2];
-  if (p->msmall) {
-    const double V = p->box[0] * p->box[1] * p->box[2];
-    const bool q32s = p->q32_nodes[0] > 0;
-    PoissonConsts pc;
-    for (int a = 0; a < 3; ++a) pc.two_pi_over_L[a] = 2.0 * M_PI / p->box[a];
-    pc.inv_4beta2 = 1.0 / (4.0 * p->cfg.beta * p->cfg.beta);
-    SmallArgs sa;
-    for (int a = 0; a < 3; ++a) {
-      sa.K[a] = g.K[a];
-      sa.nodes[a] = q32s ? p->q32_nodes[a] : 0;
-      sa.ih[a] = g.K[a] / p->box[a];
-    }
-    sa.scale = q32s ? p->q32_scale : 1.0;
-    sa.pre = p->cfg.coulomb_k / (2.0 * V);
-    sa.fmul = q32s ? p->cfg.coulomb_k / V : 1.0;
-    sa.fscale = q32s ? 1.0 : p->cfg.coulomb_k / V;
-    const bool want_virial = !(p->cfg.flags & DPLR_LR_NO_VIRIAL) && virial;
-    ProfScope ps(p, 16);
-    hipLaunchKernelGGL((k_mixed_small<T, P>), dim3(1), dim3(1024), p->lds_small, s, (const T*)ion_pos,
-                       (const T*)ion_q, (const T*)wc_pos, (const T*)wc_q, n_ion, n, (const double*)p->G, pc, sa,
-                       energy, want_virial ? virial : (double*)nullptr, (T*)ion_force, (T*)wc_force,
-                       (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
-    return DPLR_LR_OK;
-  }
   const double ih[3] = {g.K[0] / p->box[0], g.K[1] / p->box[1], g.K[2] / p->box[2]};
   cpx<T>* spec = reinterpret_cast<cpx<T>*>(p->mspec);
   cpx<T>* field = reinterpret_cast<cpx<T>*>(p->mfield);
@@ -784,23 +755,6 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
       free_all(p);
       delete p;
       return sm;
-    }
-    // small meshes and particle counts: the whole step in one workgroup
-    p->lds_small = 3 * cs * ntot;
-    if (p->lds_small + 4096 <= p->lds_budget && cfg->capacity <= kSmallMaxParticles) {
-      const void* f = nullptr;
-      switch (cfg->order) {
-#define DPLR_SMALL(PP) \
-  case PP: f = p->fp64 ? (const void*)k_mixed_small<double, PP> : (const void*)k_mixed_small<float, PP>; break;
-        DPLR_SMALL(2) DPLR_SMALL(3) DPLR_SMALL(4) DPLR_SMALL(5) DPLR_SMALL(6) DPLR_SMALL(7) DPLR_SMALL(8)
-#undef DPLR_SMALL
-      }
-      p->msmall = true;
-      if (p->lds_small > 65536 &&
-          hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_small) != hipSuccess) {
-        (void)hipGetLastError();
-        p->msmall = false;
-      }
     }
     *out = p;
     return DPLR_LR_OK;
@@ -981,7 +935,7 @@ dplr_lr_status dplr_lr_profile_read(dplr_lr_plan p, double* ms, int64_t* calls, 
   }
   if (n) *n = kNumStages;
   if (reset) {
-    for (int i = 0; i < 20; ++i) { p->prof_ms[i] = 0; p->prof_calls[i] = 0; }
+    for (int i = 0; i < 16; ++i) { p->prof_ms[i] = 0; p->prof_calls[i] = 0; }
   }
   return DPLR_LR_OK;
 }

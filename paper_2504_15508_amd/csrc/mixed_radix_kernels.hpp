@@ -349,259 +349,4 @@ __global__ void __launch_bounds__(256) k_mixed_gather(const T* __restrict__ ion_
   for (int a = 0; a < 3; ++a) out[a] = accumulate ? out[a] + v[a] : v[a];
 }
 
-// ----------------------------------------------------------------------------
-// The whole step in one workgroup, for meshes small enough to stay in LDS
-// (the paper's per-node grids: 768 to 2,592 points).  Three LDS buffers of
-// ntot complex values: A holds the charge spectrum, B the fixed-point mesh
-// and then one field component at a time, C is the ping-pong buffer of the
-// transforms.  Same arithmetic as the multi-kernel path: fixed-point spread
-// (LDS integer atomics), self-sorting transforms (or the int32-quantised
-// direct sums), the ik multiply with FP64 energy/virial sums, the inverse
-// transform of one component, and its gather; the energy/virial reduction
-// is a fixed tree over the block.  Launch: one block of 1024 threads.
-// ----------------------------------------------------------------------------
-template <typename T, int R>
-__device__ __forceinline__ void stage_rows(const cpx<T>* __restrict__ a, cpx<T>* __restrict__ b, int N, int stride,
-                                           int rows, int p, int sign) {
-  const int nb = N / R;
-  cpx<T> w[R];
-#pragma unroll
-  for (int t = 0; t < R; ++t) w[t] = unit_root<T>(t, R, sign);
-  for (int it = threadIdx.x; it < rows * nb; it += blockDim.x) {
-    const int r = it / nb, i = it - r * nb;
-    const int base = (r / stride) * stride * N + (r % stride);
-    const int k = i % p;
-    cpx<T> u[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      u[q] = a[base + (i + q * nb) * stride];
-      if (q > 0 && k > 0) u[q] = cmul(u[q], unit_root<T>((q * k) % (p * R), p * R, sign));
-    }
-    const int j = (i - k) * R + k;
-#pragma unroll
-    for (int s2 = 0; s2 < R; ++s2) {
-      cpx<T> v = u[0];
-#pragma unroll
-      for (int q = 1; q < R; ++q) v = cadd(v, cmul(u[q], w[(q * s2) % R]));
-      b[base + (j + s2 * p) * stride] = v;
-    }
-  }
-}
-
-// One axis of a 3D transform of x (in place, tmp as scratch), all rows at once.
-template <typename T>
-__device__ void small_axis(cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, int N, int stride, int ntot, int sign,
-                           int nodes, double scale) {
-  const int rows = ntot / N;
-  cpx<T>* a = x;
-  cpx<T>* b = tmp;
-  if (nodes > 0) {
-    // int32-quantised node-block sums (as k_mixed_dft_q32)
-    const int seg = N / nodes;
-    const T sc = (T)scale;
-    for (int it = threadIdx.x; it < rows * N; it += blockDim.x) {
-      const int r = it / N, k = it - r * N;
-      const int base = (r / stride) * stride * N + (r % stride);
-      long long acc_re = 0, acc_im = 0;
-      for (int bk = 0; bk < nodes; ++bk) {
-        cpx<T> s = {(T)0, (T)0};
-        for (int n = bk * seg; n < (bk + 1) * seg; ++n)
-          s = cadd(s, cmul(a[base + n * stride], unit_root<T>((n * k) % N, N, sign)));
-        acc_re += (long long)fmin(fmax((double)rint(s.x * sc), -2147483648.0), 2147483647.0);
-        acc_im += (long long)fmin(fmax((double)rint(s.y * sc), -2147483648.0), 2147483647.0);
-      }
-      b[base + k * stride] = cpx<T>{(T)((double)acc_re / scale), (T)((double)acc_im / scale)};
-    }
-    __syncthreads();
-    a = tmp;
-    b = x;
-  } else {
-    int p = 1, rem = N;
-    while (rem > 1) {
-      const int R = (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3 : 5;
-      switch (R) {
-        case 4: stage_rows<T, 4>(a, b, N, stride, rows, p, sign); break;
-        case 2: stage_rows<T, 2>(a, b, N, stride, rows, p, sign); break;
-        case 3: stage_rows<T, 3>(a, b, N, stride, rows, p, sign); break;
-        default: stage_rows<T, 5>(a, b, N, stride, rows, p, sign); break;
-      }
-      __syncthreads();
-      cpx<T>* t = a;
-      a = b;
-      b = t;
-      p *= R;
-      rem /= R;
-    }
-  }
-  if (a != x) {
-    for (int e = threadIdx.x; e < ntot; e += blockDim.x) x[e] = a[e];
-    __syncthreads();
-  }
-}
-
-template <typename T>
-__device__ void small_transform(cpx<T>* x, cpx<T>* tmp, const int K[3], int ntot, int sign, const int nodes[3],
-                                double scale) {
-  const int stride[3] = {1, K[0], K[0] * K[1]};
-  for (int a = 0; a < 3; ++a) small_axis<T>(x, tmp, K[a], stride[a], ntot, sign, nodes[a], scale);
-}
-
-struct SmallArgs {
-  int K[3];
-  int nodes[3];     // int32-quantised transforms: node blocks per axis (0: exact)
-  double scale;     // their scale
-  double ih[3];     // K / L per axis
-  double pre;       // k_e / (2V)
-  double fmul;      // factor of the field spectra (1, or k_e / V when quantised)
-  double fscale;    // force factor (k_e / V, or 1 when quantised)
-};
-
-template <typename T, int P>
-__global__ void __launch_bounds__(1024) k_mixed_small(const T* __restrict__ ion_pos, const T* __restrict__ ion_q,
-                                                      const T* __restrict__ wc_pos, const T* __restrict__ wc_q,
-                                                      int64_t n_ion, int64_t n, const double* __restrict__ G,
-                                                      PoissonConsts pc, SmallArgs sa, double* __restrict__ energy,
-                                                      double* __restrict__ virial, T* __restrict__ ion_f,
-                                                      T* __restrict__ wc_f, int accumulate) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int Kx = sa.K[0], Ky = sa.K[1], Kz = sa.K[2];
-  const int ntot = Kx * Ky * Kz;
-  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem);
-  cpx<T>* B = A + ntot;
-  cpx<T>* C = B + ntot;
-  unsigned long long* mesh = reinterpret_cast<unsigned long long*>(B);
-  __shared__ double red[7][16];
-  for (int e = threadIdx.x; e < ntot; e += blockDim.x) mesh[e] = 0ull;
-  __syncthreads();
-  // spread
-  for (int64_t it = threadIdx.x; it < n * P; it += blockDim.x) {
-    const int64_t i = it / P;
-    const int tz = (int)(it - i * P);
-    const T* r = (i < n_ion) ? (ion_pos + 3 * i) : (wc_pos + 3 * (i - n_ion));
-    const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
-    double d[3];
-    const int sx = mixed_stencil<P>((double)r[0], sa.ih[0], Kx, d[0]);
-    const int sy = mixed_stencil<P>((double)r[1], sa.ih[1], Ky, d[1]);
-    const int sz = mixed_stencil<P>((double)r[2], sa.ih[2], Kz, d[2]);
-    T wx[P], wy[P], wz[P];
-    bspline_weights<T, P>((T)d[0], wx);
-    bspline_weights<T, P>((T)d[1], wy);
-    bspline_weights<T, P>((T)d[2], wz);
-    T wzt = wz[0];
-#pragma unroll
-    for (int t = 1; t < P; ++t) wzt = (tz == t) ? wz[t] : wzt;
-    const int gz = (sz + tz) % Kz;
-    const T qz = q * wzt;
-    for (int ty = 0; ty < P; ++ty) {
-      const int gy = (sy + ty) % Ky;
-      const T qyz = qz * wy[ty];
-      unsigned long long* row = mesh + (gz * Ky + gy) * Kx;
-#pragma unroll
-      for (int tx = 0; tx < P; ++tx) {
-        const long long v = llrint((double)(qyz * wx[tx]) * kMixedFixedScale);
-        atomicAdd(row + (sx + tx) % Kx, (unsigned long long)v);
-      }
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < ntot; e += blockDim.x)
-    A[e] = cpx<T>{(T)((double)(long long)mesh[e] * (1.0 / kMixedFixedScale)), (T)0};
-  __syncthreads();
-  small_transform<T>(A, C, sa.K, ntot, -1, sa.nodes, sa.scale);
-  // energy and virial partials of this thread
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int e = threadIdx.x; e < ntot; e += blockDim.x) {
-    const int idx[3] = {e % Kx, (e / Kx) % Ky, e / (Kx * Ky)};
-    int an[3];
-    double k[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int nn = (idx[a] <= sa.K[a] / 2) ? idx[a] : idx[a] - sa.K[a];
-      an[a] = nn < 0 ? -nn : nn;
-      k[a] = pc.two_pi_over_L[a] * (double)nn;
-    }
-    const double g = G[((size_t)an[0] * (Ky / 2 + 1) + an[1]) * (Kz / 2 + 1) + an[2]];
-    const double qx = (double)A[e].x, qy = (double)A[e].y;
-    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-    if (k2 > 0.0) {
-      const double en = g * (qx * qx + qy * qy);
-      const double c = 2.0 * (1.0 + k2 * pc.inv_4beta2) / k2;
-      acc[0] += en;
-      acc[1] += en * (1.0 - c * k[0] * k[0]);
-      acc[2] += en * (1.0 - c * k[1] * k[1]);
-      acc[3] += en * (1.0 - c * k[2] * k[2]);
-      acc[4] += -en * c * k[0] * k[1];
-      acc[5] += -en * c * k[0] * k[2];
-      acc[6] += -en * c * k[1] * k[2];
-    }
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < 7; ++c) {
-    double v = acc[c];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) red[c][wv] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t[7];
-    for (int c = 0; c < 7; ++c) {
-      double v = 0.0;
-      for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) v += red[c][w2];
-      t[c] = v;
-    }
-    *energy = sa.pre * t[0];
-    if (virial)
-      for (int c = 1; c < 7; ++c) virial[c - 1] = sa.pre * t[c];
-  }
-  // one field component at a time: spectrum, inverse transform, gather
-  for (int a = 0; a < 3; ++a) {
-    for (int e = threadIdx.x; e < ntot; e += blockDim.x) {
-      const int ia = (a == 0) ? e % Kx : (a == 1) ? (e / Kx) % Ky : e / (Kx * Ky);
-      const int Ka = sa.K[a];
-      const int nn = (ia <= Ka / 2) ? ia : ia - Ka;
-      const int idx[3] = {e % Kx, (e / Kx) % Ky, e / (Kx * Ky)};
-      int an[3];
-#pragma unroll
-      for (int b2 = 0; b2 < 3; ++b2) {
-        const int m = (idx[b2] <= sa.K[b2] / 2) ? idx[b2] : idx[b2] - sa.K[b2];
-        an[b2] = m < 0 ? -m : m;
-      }
-      const double kd = ((Ka & 1) == 0 && ia == Ka / 2) ? 0.0 : pc.two_pi_over_L[a] * (double)nn;
-      const double g = G[((size_t)an[0] * (Ky / 2 + 1) + an[1]) * (Kz / 2 + 1) + an[2]];
-      const T f = (T)(sa.fmul * (kd * g));
-      B[e] = cpx<T>{f * A[e].y, -f * A[e].x};
-    }
-    __syncthreads();
-    small_transform<T>(B, C, sa.K, ntot, +1, sa.nodes, sa.scale);
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-      const T* r = (i < n_ion) ? (ion_pos + 3 * i) : (wc_pos + 3 * (i - n_ion));
-      const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
-      double d[3];
-      const int sx = mixed_stencil<P>((double)r[0], sa.ih[0], Kx, d[0]);
-      const int sy = mixed_stencil<P>((double)r[1], sa.ih[1], Ky, d[1]);
-      const int sz = mixed_stencil<P>((double)r[2], sa.ih[2], Kz, d[2]);
-      T wx[P], wy[P], wz[P];
-      bspline_weights<T, P>((T)d[0], wx);
-      bspline_weights<T, P>((T)d[1], wy);
-      bspline_weights<T, P>((T)d[2], wz);
-      T f = 0;
-      for (int tz = 0; tz < P; ++tz) {
-        const int gz = (sz + tz) % Kz;
-        for (int ty = 0; ty < P; ++ty) {
-          const int gy = (sy + ty) % Ky;
-          const T wyz = wz[tz] * wy[ty];
-          const cpx<T>* row = B + (gz * Ky + gy) * Kx;
-#pragma unroll
-          for (int tx = 0; tx < P; ++tx) f += wyz * wx[tx] * row[(sx + tx) % Kx].x;
-        }
-      }
-      T* out = (i < n_ion) ? (ion_f + 3 * i) : (wc_f + 3 * (i - n_ion));
-      const T v = (T)sa.fscale * q * f;
-      out[a] = accumulate ? out[a] + v : v;
-    }
-    __syncthreads();
-  }
-}
-
 }  // namespace dplr

@@ -20,30 +20,6 @@ pytestmark = pytest.mark.gpu
 
 FP32_TOL_F, FP32_TOL_E = 1e-5, 2e-6
 PAPER_GRIDS = [(8, 12, 8), (10, 15, 10), (12, 18, 12)]
-# plans with a mesh that fits in LDS and a capacity of at most 8,192 charges
-# run the whole step in one workgroup ("fused"); a larger capacity selects
-# the multi-kernel path ("multi") for the same inputs
-CAPACITY = {"fused": None, "multi": 10000}
-
-
-def check_path(torch, s, mesh, order, precision, path, tol_f, tol_e, nodes=None):
-    import paper_2504_15508_amd as dl
-    cap = CAPACITY[path] or s.n
-    plan = dl.Plan(mesh, order=order, beta=BETA, coulomb_k=KE, precision=precision, capacity=cap)
-    plan.set_box(s.box)
-    if nodes:
-        plan.set_fft_int32(nodes, 1e7)
-    E, fi, fw, W, _ = run_gpu(torch, s, mesh, order, precision, plan=plan)
-    ref = s.rounded(np.float32) if precision == "fp32" else s
-    if nodes:
-        E0, F0, W0 = pppm.pppm_int32(ref.all_pos(), ref.all_q(), ref.box, mesh, order, BETA, KE, nodes, 1e7)
-    else:
-        E0, F0, W0 = pppm.pppm(ref.all_pos(), ref.all_q(), ref.box, mesh, order, BETA, KE)
-    F = np.concatenate([fi, fw])
-    dE, dF, dW = abs(E - E0) / abs(E0), rel(F, F0), np.abs(W - W0).max() / abs(E0)
-    print(f"{path} {mesh} p={order} {precision} int32={nodes}: dE={dE:.2e} dF={dF:.2e} dW={dW:.2e}", flush=True)
-    assert dF <= tol_f and dE <= tol_e and dW <= tol_e
-    return F0
 
 
 def small_water():
@@ -52,21 +28,12 @@ def small_water():
 
 @pytest.mark.parametrize("mesh", PAPER_GRIDS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("path", ["fused", "multi"])
-def test_paper_grids(torch_dev, mesh, precision, path):
+def test_paper_grids(torch_dev, mesh, precision):
     s = small_water()
     if precision == "fp64":
-        check_path(torch_dev, s, mesh, 5, "fp64", path, 1e-9, 1e-9)
+        check_vs_pppm(torch_dev, s, mesh, 5, "fp64", 1e-9, 1e-9, 1e-9)
     else:
-        check_path(torch_dev, s, mesh, 5, "fp32", path, FP32_TOL_F, FP32_TOL_E)
-
-
-@pytest.mark.parametrize("mesh,order", [((8, 8, 8), 8), ((6, 5, 4), 2), ((16, 10, 9), 7)])
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_fused_step_orders(torch_dev, mesh, order, precision):
-    s = small_water()
-    tol = (1e-9, 1e-9) if precision == "fp64" else (FP32_TOL_F, FP32_TOL_E)
-    check_path(torch_dev, s, mesh, order, precision, "fused", *tol)
+        check_vs_pppm(torch_dev, s, mesh, 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
 
 
 @pytest.mark.parametrize("mesh,order", [((15, 25, 27), 3), ((45, 30, 20), 7), ((8, 8, 8), 5), ((9, 10, 6), 6),
@@ -108,15 +75,13 @@ def test_paper_grid_error_vs_ewald_is_reported(torch_dev):
     assert errs[0] > errs[1] > errs[2] > errs[3]
 
 
-@pytest.mark.parametrize("path", ["fused", "multi"])
-def test_empty_accumulate_no_virial_and_repeatability(torch_dev, path):
+def test_empty_accumulate_no_virial_and_repeatability(torch_dev):
     import paper_2504_15508_amd as dl
     torch = torch_dev
     s = small_water()
     r = s.rounded(np.float32)
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
-    cap = CAPACITY[path] or s.n
-    plan = dl.Plan((10, 15, 10), order=5, beta=BETA, coulomb_k=KE, precision="fp32", capacity=cap)
+    plan = dl.Plan((10, 15, 10), order=5, beta=BETA, coulomb_k=KE, precision="fp32", capacity=s.n)
     plan.set_box(s.box)
     E1, fi1, fw1, W1 = plan.compute(t(r.ion_pos), t(r.ion_q), t(r.wc_pos), t(r.wc_q))
     E2, fi2, fw2, W2 = plan.compute(t(r.ion_pos), t(r.ion_q), t(r.wc_pos), t(r.wc_q))
@@ -135,7 +100,7 @@ def test_empty_accumulate_no_virial_and_repeatability(torch_dev, path):
     torch.cuda.synchronize()
     assert torch.equal(fi1, fi3) and float(E1) == float(E3)
     # accumulate into given outputs; no virial
-    pa = dl.Plan((10, 15, 10), order=5, beta=BETA, coulomb_k=KE, precision="fp32", capacity=cap,
+    pa = dl.Plan((10, 15, 10), order=5, beta=BETA, coulomb_k=KE, precision="fp32", capacity=s.n,
                  flags=dl._lib.ACCUMULATE | dl._lib.NO_VIRIAL)
     pa.set_box(s.box)
     base_i = torch.full_like(fi1, 0.5)
@@ -170,16 +135,14 @@ def test_mixed_mesh_rejects_ad_and_bad_sizes(torch_dev):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("mesh", PAPER_GRIDS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("path", ["fused", "multi"])
-def test_int32_transforms_match_oracle(torch_dev, mesh, precision, path):
+def test_int32_transforms_match_oracle(torch_dev, mesh, precision):
     import paper_2504_15508_amd as dl
     torch = torch_dev
     s = small_water()
     ref = s.rounded(np.float32) if precision == "fp32" else s
     dt = torch.float64 if precision == "fp64" else torch.float32
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
-    plan = dl.Plan(mesh, order=5, beta=BETA, coulomb_k=KE, precision=precision,
-                   capacity=CAPACITY[path] or s.n)
+    plan = dl.Plan(mesh, order=5, beta=BETA, coulomb_k=KE, precision=precision, capacity=s.n)
     plan.set_box(s.box)
     plan.set_fft_int32((2, 3, 2), 1e7)
     E, fi, fw, W = plan.compute(t(ref.ion_pos), t(ref.ion_q), t(ref.wc_pos), t(ref.wc_q))
@@ -189,7 +152,7 @@ def test_int32_transforms_match_oracle(torch_dev, mesh, precision, path):
     E1, F1, _ = pppm.pppm(ref.all_pos(), ref.all_q(), ref.box, mesh, 5, BETA, KE)
     dE, dF = abs(float(E) - E0) / abs(E0), rel(F, F0)
     dW = np.abs(W.cpu().numpy() - W0).max() / abs(E0)
-    print(f"int32 {path} {mesh} {precision}: dE={dE:.2e} dF={dF:.2e} dW={dW:.2e}  "
+    print(f"int32 {mesh} {precision}: dE={dE:.2e} dF={dF:.2e} dW={dW:.2e}  "
           f"(int32 vs exact transforms: {rel(F0, F1):.2e})", flush=True)
     if precision == "fp64":
         assert dF <= 1e-7 and dE <= 1e-8 and dW <= 1e-8
