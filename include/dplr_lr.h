@@ -179,6 +179,9 @@ int64_t dplr_lr_workspace_bytes(dplr_lr_plan p);
  *                         whose z planes do not fit in LDS also apply the
  *                         inverse y transform here; DPLR_LR_DIFF_AD plans
  *                         fill only the first, the potential).
+ * Mixed-radix plans (meshes outside the powers of two from 16 to 512) keep
+ * only DPLR_LR_BUF_INFLUENCE: debug_size returns -1 for the others and
+ * debug_copy E_INVALID.
  * Copies `bytes` bytes (at most the buffer size, else E_INVALID) into the
  * device pointer dst, stream-ordered. */
 #define DPLR_LR_BUF_SPECTRUM 0

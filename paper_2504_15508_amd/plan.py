@@ -169,6 +169,9 @@ class Plan:
         """Copy of an intermediate buffer of the last compute (see include/dplr_lr.h)."""
         lib = _lib.load()
         nbytes = int(lib.dplr_lr_debug_size(self._h, which))
+        if nbytes < 0:
+            raise ValueError(f"buffer {which} is not available on this plan "
+                             "(mixed-radix plans keep only the influence table)")
         out = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         with torch.cuda.device(self.device):
             self._bind_stream()

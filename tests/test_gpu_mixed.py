@@ -193,3 +193,16 @@ def test_full_size_mixed_mesh_fp32(torch_dev):
     w = systems.workload(3)
     s = w.system()
     check_vs_pppm(torch_dev, s, (120, 120, 120), 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
+
+
+def test_mixed_plan_debug_buffers(torch_dev):
+    import paper_2504_15508_amd as dl
+    box = np.array([16.0, 16.0, 16.0])
+    plan = dl.Plan((12, 18, 12), order=5, beta=BETA, coulomb_k=KE, precision="fp64", capacity=4)
+    plan.set_box(box)
+    torch_dev.cuda.synchronize()
+    G = plan.debug_buffer(dl._lib.BUF_INFLUENCE).cpu().numpy()
+    G0 = pppm.influence(box, (12, 18, 12), BETA, 5)
+    assert np.abs(G - G0[:7, :10, :7]).max() <= 1e-13 * np.abs(G0).max()
+    with pytest.raises(ValueError, match="not available"):
+        plan.debug_buffer(dl._lib.BUF_SPECTRUM)
