@@ -153,7 +153,11 @@ struct dplr_lr_plan_s {
   long long* mmesh = nullptr; // mixed-radix path: fixed-point mesh [Kz][Ky][Kx]
   void* mspec = nullptr;      // ... its full complex spectrum
   void* mfield = nullptr;     // ... three full field spectra, transformed back in place
+  void* mpacked = nullptr;    // ... the three real fields interleaved (x, y, z, unused) per mesh point
   int mblk = 0;               // ... blocks (and partials) of the ik multiply
+  size_t lds_mplane = 0;      // ... LDS of the plane spread (0: the plane does not fit; global atomics)
+  void* mrec = nullptr;       // ... per-particle stencil offsets and charge (plane spread)
+  int* mspk = nullptr;        // ... per-particle packed stencil starts (plane spread)
   int q32_nodes[3] = {0, 0, 0};  // int32-quantised transforms: node blocks per axis (0: off)
   double q32_scale = 0.0;
   int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_ifftx = 256, thr_ixy = 256;
@@ -571,27 +575,30 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
 // inverse x/y/z transforms, energy/virial reduction, gather.
 int mixed_fft_threads(int N) { return N <= 128 ? 64 : (N <= 512 ? 128 : 256); }
 
+// packed: the last (z) pass writes the real parts interleaved there
 template <typename T>
-void launch_mixed_fft(dplr_lr_plan p, cpx<T>* data, int ncomp, int sign) {
+void launch_mixed_fft(dplr_lr_plan p, cpx<T>* data, int ncomp, int sign, T* packed) {
   const int K[3] = {p->geo.K[0], p->geo.K[1], p->geo.K[2]};
   const int64_t ntot = (int64_t)K[0] * K[1] * K[2];
   const int64_t stride[3] = {1, K[0], (int64_t)K[0] * K[1]};
   for (int a = 0; a < 3; ++a) {
     const int64_t rows = ntot / K[a];
     hipLaunchKernelGGL(k_mixed_fft_axis<T>, dim3((unsigned)rows, (unsigned)ncomp), dim3(mixed_fft_threads(K[a])),
-                       2 * sizeof(cpx<T>) * K[a], p->stream, data, K[a], stride[a], ntot, sign);
+                       2 * sizeof(cpx<T>) * K[a], p->stream, data, K[a], stride[a], ntot, sign,
+                       a == 2 ? packed : (T*)nullptr);
   }
 }
 
 template <typename T>
-void launch_mixed_dft_q32(dplr_lr_plan p, cpx<T>* data, int ncomp, int sign) {
+void launch_mixed_dft_q32(dplr_lr_plan p, cpx<T>* data, int ncomp, int sign, T* packed) {
   const int K[3] = {p->geo.K[0], p->geo.K[1], p->geo.K[2]};
   const int64_t ntot = (int64_t)K[0] * K[1] * K[2];
   const int64_t stride[3] = {1, K[0], (int64_t)K[0] * K[1]};
   for (int a = 0; a < 3; ++a) {
     const int64_t rows = ntot / K[a];
     hipLaunchKernelGGL(k_mixed_dft_q32<T>, dim3((unsigned)rows, (unsigned)ncomp), dim3(64), sizeof(cpx<T>) * K[a],
-                       p->stream, data, K[a], stride[a], ntot, sign, p->q32_nodes[a], p->q32_scale);
+                       p->stream, data, K[a], stride[a], ntot, sign, p->q32_nodes[a], p->q32_scale,
+                       a == 2 ? packed : (T*)nullptr);
   }
 }
 
@@ -612,7 +619,16 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
   // spread: one thread per (particle, stencil plane); gather: 256 / P particles per block
   const unsigned nbp = (unsigned)((n * P + 255) / 256);
   const unsigned nbg = (unsigned)((n + 256 / P - 1) / (256 / P));
-  if (n > 0) {
+  if (p->lds_mplane) {
+    // one block per z plane: spread in LDS, written straight into the spectrum buffer
+    ProfScope ps(p, 11);
+    if (n > 0)
+      hipLaunchKernelGGL((k_mixed_prep<T, P>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                         (const T*)ion_pos, (const T*)ion_q, (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0],
+                         ih[1], ih[2], g.K[0], g.K[1], g.K[2], (T4<T>*)p->mrec, p->mspk);
+    hipLaunchKernelGGL((k_mixed_spread_plane<T, P>), dim3(g.K[2]), dim3(1024), p->lds_mplane, s,
+                       (const T4<T>*)p->mrec, (const int*)p->mspk, n, g.K[0], g.K[1], g.K[2], spec);
+  } else if (n > 0) {
     ProfScope ps(p, 11);
     hipLaunchKernelGGL((k_mixed_spread<T, P>), dim3(nbp), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
                        (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], g.K[0], g.K[1], g.K[2],
@@ -620,9 +636,11 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
   }
   {
     ProfScope ps(p, 12);
-    hipLaunchKernelGGL(k_mixed_unfix<T>, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, p->mmesh, spec, ntot);
-    if (q32) launch_mixed_dft_q32<T>(p, spec, 1, -1);
-    else launch_mixed_fft<T>(p, spec, 1, -1);
+    if (!p->lds_mplane)
+      hipLaunchKernelGGL(k_mixed_unfix<T>, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, p->mmesh, spec,
+                         ntot);
+    if (q32) launch_mixed_dft_q32<T>(p, spec, 1, -1, (T*)nullptr);
+    else launch_mixed_fft<T>(p, spec, 1, -1, (T*)nullptr);
   }
   PoissonConsts pc;
   for (int a = 0; a < 3; ++a) pc.two_pi_over_L[a] = 2.0 * M_PI / p->box[a];
@@ -639,13 +657,13 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
   if (n > 0) {
     {
       ProfScope ps(p, 14);
-      if (q32) launch_mixed_dft_q32<T>(p, field, 3, +1);
-      else launch_mixed_fft<T>(p, field, 3, +1);
+      if (q32) launch_mixed_dft_q32<T>(p, field, 3, +1, (T*)p->mpacked);
+      else launch_mixed_fft<T>(p, field, 3, +1, (T*)p->mpacked);
     }
     ProfScope ps(p, 15);
     hipLaunchKernelGGL((k_mixed_gather<T, P>), dim3(nbg), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
                        (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], g.K[0], g.K[1], g.K[2],
-                       (const cpx<T>*)field, (T*)ion_force, (T*)wc_force, q32 ? (T)1 : (T)(p->cfg.coulomb_k / V),
+                       (const T4<T>*)p->mpacked, (T*)ion_force, (T*)wc_force, q32 ? (T)1 : (T)(p->cfg.coulomb_k / V),
                        (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0);
   }
   hipError_t e = hipGetLastError();
@@ -742,7 +760,8 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
     void* tmp = nullptr;
     if (sm == DPLR_LR_OK) { sm = alloc(p, &tmp, sizeof(long long) * ntot, "mixed-radix mesh"); p->mmesh = (long long*)tmp; }
     if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mspec, cs * ntot, "mixed-radix spectrum"); }
-    if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mfield, 3 * cs * ntot, "mixed-radix fields"); }
+    if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mfield, 3 * cs * ntot, "mixed-radix field spectra"); }
+    if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mpacked, 4 * ts * ntot, "mixed-radix fields"); }
     if (sm == DPLR_LR_OK) { sm = alloc(p, &tmp, sizeof(double) * ng, "influence"); p->G = (double*)tmp; }
     if (sm == DPLR_LR_OK) { sm = alloc(p, &tmp, sizeof(double) * 8 * p->mblk, "partials"); p->partials = (double*)tmp; }
     if (sm == DPLR_LR_OK) {
@@ -755,6 +774,35 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
       free_all(p);
       delete p;
       return sm;
+    }
+    // plane spread when an xy plane of 64-bit accumulators fits in LDS
+    const size_t lp = sizeof(unsigned long long) * (size_t)g.K[0] * g.K[1];
+    if (lp + 10240 <= p->lds_budget) {
+      const void* f = nullptr;
+      switch (cfg->order) {
+#define DPLR_PLANE(PP)                                                                                     \
+  case PP:                                                                                                 \
+    f = p->fp64 ? (const void*)k_mixed_spread_plane<double, PP> : (const void*)k_mixed_spread_plane<float, PP>; \
+    break;
+        DPLR_PLANE(2) DPLR_PLANE(3) DPLR_PLANE(4) DPLR_PLANE(5) DPLR_PLANE(6) DPLR_PLANE(7) DPLR_PLANE(8)
+#undef DPLR_PLANE
+      }
+      p->lds_mplane = lp;
+      if (lp > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp) != hipSuccess) {
+        (void)hipGetLastError();
+        p->lds_mplane = 0;
+      }
+      const size_t capn = (size_t)std::max<int64_t>(cfg->capacity, 1);
+      void* t2 = nullptr;
+      dplr_lr_status sr = DPLR_LR_OK;
+      if (p->lds_mplane) sr = alloc(p, &p->mrec, 4 * ts * capn, "mixed-radix stencil records");
+      if (p->lds_mplane && sr == DPLR_LR_OK) { sr = alloc(p, &t2, sizeof(int) * capn, "mixed-radix stencil starts"); p->mspk = (int*)t2; }
+      if (sr != DPLR_LR_OK) {
+        g_global_error = p->err;
+        free_all(p);
+        delete p;
+        return sr;
+      }
     }
     *out = p;
     return DPLR_LR_OK;

@@ -88,6 +88,98 @@ __global__ void __launch_bounds__(256) k_mixed_spread(const T* __restrict__ ion_
   }
 }
 
+// Per-particle stencil record, computed once per call: the offsets d (plan
+// precision) and the charge in rec, the stencil starts packed as
+// s_x | s_y << 10 | s_z << 20 in spk (mesh sizes <= 512).
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_mixed_prep(const T* __restrict__ ion_pos, const T* __restrict__ ion_q,
+                                                    const T* __restrict__ wc_pos, const T* __restrict__ wc_q,
+                                                    int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
+                                                    int Kx, int Ky, int Kz, T4<T>* __restrict__ rec,
+                                                    int* __restrict__ spk) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T* r = (i < n_ion) ? (ion_pos + 3 * i) : (wc_pos + 3 * (i - n_ion));
+  const T q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
+  double d[3];
+  const int sx = mixed_stencil<P>((double)r[0], ihx, Kx, d[0]);
+  const int sy = mixed_stencil<P>((double)r[1], ihy, Ky, d[1]);
+  const int sz = mixed_stencil<P>((double)r[2], ihz, Kz, d[2]);
+  rec[i] = T4<T>{(T)d[0], (T)d[1], (T)d[2], q};
+  spk[i] = sx | (sy << 10) | (sz << 20);
+}
+
+// Spread by z planes, for meshes whose xy plane of 64-bit accumulators fits
+// in LDS: block z scans the packed stencil starts of every particle, queues
+// (in LDS) those whose stencil covers plane z, and once 1024 are queued (or
+// at the end) adds their P^2 plane terms with LDS integer atomics, so the
+// weight arithmetic runs on full waves.  Integer sums are exact and order
+// independent.  The plane is written as complex values (imaginary part 0)
+// into the spectrum buffer.  Grid Kz blocks of 1024 threads; LDS Kx Ky
+// 64-bit words.
+template <typename T, int P>
+__global__ void __launch_bounds__(1024) k_mixed_spread_plane(const T4<T>* __restrict__ rec,
+                                                             const int* __restrict__ spk, int64_t n, int Kx, int Ky,
+                                                             int Kz, cpx<T>* __restrict__ spec) {
+  extern __shared__ __align__(16) unsigned long long pl[];
+  __shared__ int queue[2048];
+  __shared__ int qn;
+  const int z = blockIdx.x;
+  const int nxy = Kx * Ky;
+  for (int e = threadIdx.x; e < nxy; e += blockDim.x) pl[e] = 0ull;
+  if (threadIdx.x == 0) qn = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < n; base += blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    if (i < n) {
+      int tz = z - (spk[i] >> 20);
+      if (tz < 0) tz += Kz;
+      if (tz < P) queue[atomicAdd(&qn, 1)] = (int)i;
+    }
+    __syncthreads();
+    const int m = qn;  // < 2048: at most 1023 left over plus 1024 new
+    __syncthreads();   // every thread has read qn before the next chunk adds to it
+    if (m >= (int)blockDim.x || base + blockDim.x >= n) {
+      for (int k = threadIdx.x; k < m; k += blockDim.x) {
+        const int j = queue[k];
+        const T4<T> rc = rec[j];
+        const int pk = spk[j];
+        const int sx = pk & 1023, sy = (pk >> 10) & 1023;
+        int tz = z - (pk >> 20);
+        if (tz < 0) tz += Kz;
+        T wx[P], wy[P], wz[P];
+        bspline_weights<T, P>(rc.x, wx);
+        bspline_weights<T, P>(rc.y, wy);
+        bspline_weights<T, P>(rc.z, wz);
+        T wzt = wz[0];
+#pragma unroll
+        for (int t = 1; t < P; ++t) wzt = (tz == t) ? wz[t] : wzt;
+        const T qz = rc.w * wzt;
+        int gx[P];
+#pragma unroll
+        for (int t = 0; t < P; ++t) gx[t] = (sx + t) % Kx;
+        for (int ty = 0; ty < P; ++ty) {
+          const int gy = (sy + ty) % Ky;
+          const T qyz = qz * wy[ty];
+          unsigned long long* row = pl + gy * Kx;
+#pragma unroll
+          for (int tx = 0; tx < P; ++tx) {
+            const long long v = llrint((double)(qyz * wx[tx]) * kMixedFixedScale);
+            atomicAdd(row + gx[tx], (unsigned long long)v);
+          }
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) qn = 0;
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  cpx<T>* out = spec + (int64_t)z * nxy;
+  for (int e = threadIdx.x; e < nxy; e += blockDim.x)
+    out[e] = cpx<T>{(T)((double)(long long)pl[e] * (1.0 / kMixedFixedScale)), (T)0};
+}
+
 // Fixed point -> complex mesh; clears the accumulators for the next call.
 template <typename T>
 __global__ void __launch_bounds__(256) k_mixed_unfix(long long* __restrict__ mesh, cpx<T>* __restrict__ out,
@@ -114,7 +206,10 @@ __device__ __forceinline__ cpx<T> unit_root(int a, int b, int sign) {
 // X[k] = sum_n x[n] exp(sign 2 pi i n k / N).  Row r of component c starts
 // at c * comp_stride + (r / stride) * stride * N + r % stride and its
 // elements are stride apart (stride 1: x rows, Kx: y columns, Kx Ky: z
-// columns).  Grid (rows, components); LDS 2 N complex values.
+// columns).  Grid (rows, components); LDS 2 N complex values.  With packed
+// != nullptr the real parts are written instead to packed[4 e + c] (e the
+// mesh index of the element, c the component): the last inverse pass leaves
+// the three fields interleaved for the gather.
 // Self-sorting stages: with p points already transformed, butterfly i
 // (0 <= i < N/R) takes x[i + q N/R], q < R, applies the twiddles
 // exp(sign 2 pi i q k / (p R)) with k = i mod p, a length-R DFT, and stores
@@ -147,12 +242,13 @@ __device__ __forceinline__ void stockham_stage(const cpx<T>* __restrict__ a, cpx
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_mixed_fft_axis(cpx<T>* __restrict__ data, int N, int64_t stride,
-                                                        int64_t comp_stride, int sign) {
+                                                        int64_t comp_stride, int sign, T* __restrict__ packed) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<T>* a = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* b = a + N;
   const int64_t r = blockIdx.x;
-  cpx<T>* row = data + (int64_t)blockIdx.y * comp_stride + (r / stride) * stride * N + (r % stride);
+  const int64_t rbase = (r / stride) * stride * N + (r % stride);
+  cpx<T>* row = data + (int64_t)blockIdx.y * comp_stride + rbase;
   for (int e = threadIdx.x; e < N; e += blockDim.x) a[e] = row[(int64_t)e * stride];
   __syncthreads();
   int p = 1, rem = N;
@@ -171,7 +267,11 @@ __global__ void __launch_bounds__(256) k_mixed_fft_axis(cpx<T>* __restrict__ dat
     p *= R;
     rem /= R;
   }
-  for (int e = threadIdx.x; e < N; e += blockDim.x) row[(int64_t)e * stride] = a[e];
+  if (packed) {
+    for (int e = threadIdx.x; e < N; e += blockDim.x) packed[4 * (rbase + (int64_t)e * stride) + blockIdx.y] = a[e].x;
+  } else {
+    for (int e = threadIdx.x; e < N; e += blockDim.x) row[(int64_t)e * stride] = a[e];
+  }
 }
 
 // The same row transform taken as the paper's hardware-offloaded FFT forms it
@@ -182,14 +282,17 @@ __global__ void __launch_bounds__(256) k_mixed_fft_axis(cpx<T>* __restrict__ dat
 // is scaled by `scale`, rounded to the nearest integer and clamped to the
 // int32 range (real and imaginary parts apart), the integers are summed over
 // the blocks exactly and the sum is divided by `scale`.  Direct sums, O(N)
-// per output.  Grid (rows, components); LDS N complex values.
+// per output.  Grid (rows, components); LDS N complex values; packed as in
+// k_mixed_fft_axis.
 template <typename T>
 __global__ void __launch_bounds__(256) k_mixed_dft_q32(cpx<T>* __restrict__ data, int N, int64_t stride,
-                                                       int64_t comp_stride, int sign, int nodes, double scale) {
+                                                       int64_t comp_stride, int sign, int nodes, double scale,
+                                                       T* __restrict__ packed) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<T>* a = reinterpret_cast<cpx<T>*>(smem);
   const int64_t r = blockIdx.x;
-  cpx<T>* row = data + (int64_t)blockIdx.y * comp_stride + (r / stride) * stride * N + (r % stride);
+  const int64_t rbase = (r / stride) * stride * N + (r % stride);
+  cpx<T>* row = data + (int64_t)blockIdx.y * comp_stride + rbase;
   for (int e = threadIdx.x; e < N; e += blockDim.x) a[e] = row[(int64_t)e * stride];
   __syncthreads();
   const int seg = N / nodes;
@@ -204,7 +307,9 @@ __global__ void __launch_bounds__(256) k_mixed_dft_q32(cpx<T>* __restrict__ data
       acc_re += (long long)fmin(fmax((double)rint(s.x * sc), -2147483648.0), 2147483647.0);
       acc_im += (long long)fmin(fmax((double)rint(s.y * sc), -2147483648.0), 2147483647.0);
     }
-    row[(int64_t)k * stride] = cpx<T>{(T)((double)acc_re / scale), (T)((double)acc_im / scale)};
+    const cpx<T> v = {(T)((double)acc_re / scale), (T)((double)acc_im / scale)};
+    if (packed) packed[4 * (rbase + (int64_t)k * stride) + blockIdx.y] = v.x;
+    else row[(int64_t)k * stride] = v;
   }
 }
 
@@ -280,14 +385,15 @@ __global__ void __launch_bounds__(256) k_mixed_reduce(const double* __restrict__
   reduce_partials(partials, nblk, pre, energy, virial, red);
 }
 
-// F_ja = (k_e q_j / V) sum_g W(u_j - g) Re E_a(g), caller's order.  Block of
+// F_ja = (k_e q_j / V) sum_g W(u_j - g) E_a(g), caller's order, from the
+// interleaved real fields (x, y, z, unused) the last inverse pass wrote.  Block of
 // 256 threads: 256 / P particles, one thread per (particle, stencil plane tz);
 // the P plane sums of a particle are added in tz order (deterministic).
 template <typename T, int P>
 __global__ void __launch_bounds__(256) k_mixed_gather(const T* __restrict__ ion_pos, const T* __restrict__ ion_q,
                                                       const T* __restrict__ wc_pos, const T* __restrict__ wc_q,
                                                       int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
-                                                      int Kx, int Ky, int Kz, const cpx<T>* __restrict__ Ef,
+                                                      int Kx, int Ky, int Kz, const T4<T>* __restrict__ Ef,
                                                       T* __restrict__ ion_f, T* __restrict__ wc_f, T fscale,
                                                       int accumulate) {
   __shared__ T part[256][3];
@@ -297,7 +403,6 @@ __global__ void __launch_bounds__(256) k_mixed_gather(const T* __restrict__ ion_
   const bool on = jl < PPB && i < n;
   T f0 = 0, f1 = 0, f2 = 0;
   if (on) {
-  const int64_t ntot = (int64_t)Kx * Ky * Kz;
   const T* r = (i < n_ion) ? (ion_pos + 3 * i) : (wc_pos + 3 * (i - n_ion));
   double d[3];
   const int sx = mixed_stencil<P>((double)r[0], ihx, Kx, d[0]);
@@ -321,11 +426,11 @@ __global__ void __launch_bounds__(256) k_mixed_gather(const T* __restrict__ ion_
     const int64_t rb = ((int64_t)gz * Ky + gy) * Kx;
 #pragma unroll
     for (int tx = 0; tx < P; ++tx) {
-      const int64_t e = rb + gx[tx];
+      const T4<T> v = Ef[rb + gx[tx]];
       const T w = wyz * wx[tx];
-      f0 += w * Ef[e].x;
-      f1 += w * Ef[ntot + e].x;
-      f2 += w * Ef[2 * ntot + e].x;
+      f0 += w * v.x;
+      f1 += w * v.y;
+      f2 += w * v.z;
     }
   }
   }

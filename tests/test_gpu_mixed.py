@@ -36,8 +36,10 @@ def test_paper_grids(torch_dev, mesh, precision):
         check_vs_pppm(torch_dev, s, mesh, 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
 
 
+# (160, 135, 8) and (240, 90, 10): xy planes too large for LDS, so the
+# spread takes the global-atomic kernel instead of the plane kernel
 @pytest.mark.parametrize("mesh,order", [((15, 25, 27), 3), ((45, 30, 20), 7), ((8, 8, 8), 5), ((9, 10, 6), 6),
-                                        ((6, 5, 4), 4), ((96, 80, 75), 5)])
+                                        ((6, 5, 4), 4), ((96, 80, 75), 5), ((160, 135, 8), 5), ((240, 90, 10), 4)])
 def test_mixed_sizes_fp64(torch_dev, mesh, order):
     s = systems.water_box(512, 25.0, seed=20261129, name="water512_25A")
     s.box = np.array([25.0, 27.5, 23.0])
@@ -75,13 +77,14 @@ def test_paper_grid_error_vs_ewald_is_reported(torch_dev):
     assert errs[0] > errs[1] > errs[2] > errs[3]
 
 
-def test_empty_accumulate_no_virial_and_repeatability(torch_dev):
+@pytest.mark.parametrize("mesh", [(10, 15, 10), (160, 135, 8)])
+def test_empty_accumulate_no_virial_and_repeatability(torch_dev, mesh):
     import paper_2504_15508_amd as dl
     torch = torch_dev
     s = small_water()
     r = s.rounded(np.float32)
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
-    plan = dl.Plan((10, 15, 10), order=5, beta=BETA, coulomb_k=KE, precision="fp32", capacity=s.n)
+    plan = dl.Plan(mesh, order=5, beta=BETA, coulomb_k=KE, precision="fp32", capacity=s.n)
     plan.set_box(s.box)
     E1, fi1, fw1, W1 = plan.compute(t(r.ion_pos), t(r.ion_q), t(r.wc_pos), t(r.wc_q))
     E2, fi2, fw2, W2 = plan.compute(t(r.ion_pos), t(r.ion_q), t(r.wc_pos), t(r.wc_q))
@@ -100,7 +103,7 @@ def test_empty_accumulate_no_virial_and_repeatability(torch_dev):
     torch.cuda.synchronize()
     assert torch.equal(fi1, fi3) and float(E1) == float(E3)
     # accumulate into given outputs; no virial
-    pa = dl.Plan((10, 15, 10), order=5, beta=BETA, coulomb_k=KE, precision="fp32", capacity=s.n,
+    pa = dl.Plan(mesh, order=5, beta=BETA, coulomb_k=KE, precision="fp32", capacity=s.n,
                  flags=dl._lib.ACCUMULATE | dl._lib.NO_VIRIAL)
     pa.set_box(s.box)
     base_i = torch.full_like(fi1, 0.5)
