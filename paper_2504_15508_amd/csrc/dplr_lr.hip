@@ -573,8 +573,6 @@ dplr_lr_status launch_step(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, c
 
 // Mixed-radix path: spread, forward x/y/z transforms, ik multiply, the three
 // inverse x/y/z transforms, energy/virial reduction, gather.
-int mixed_fft_threads(int N) { return N <= 128 ? 64 : (N <= 512 ? 128 : 256); }
-
 // packed: the last (z) pass writes the real parts interleaved there
 template <typename T>
 void launch_mixed_fft(dplr_lr_plan p, cpx<T>* data, int ncomp, int sign, T* packed) {
@@ -583,9 +581,15 @@ void launch_mixed_fft(dplr_lr_plan p, cpx<T>* data, int ncomp, int sign, T* pack
   const int64_t stride[3] = {1, K[0], (int64_t)K[0] * K[1]};
   for (int a = 0; a < 3; ++a) {
     const int64_t rows = ntot / K[a];
-    hipLaunchKernelGGL(k_mixed_fft_axis<T>, dim3((unsigned)rows, (unsigned)ncomp), dim3(mixed_fft_threads(K[a])),
-                       2 * sizeof(cpx<T>) * K[a], p->stream, data, K[a], stride[a], ntot, sign,
-                       a == 2 ? packed : (T*)nullptr);
+    // columns per block: side by side in memory for the y and z passes, at
+    // most 16 and 32 KiB of LDS per buffer
+    int C = 1;
+    if (a > 0)
+      while (C < 16 && stride[a] % (2 * C) == 0 && 2 * (size_t)C * K[a] * sizeof(cpx<T>) <= 32768) C *= 2;
+    const int thr = std::min(256, std::max(64, (C * K[a] / 2 + 63) / 64 * 64));
+    hipLaunchKernelGGL(k_mixed_fft_axis<T>, dim3((unsigned)(rows / C), (unsigned)ncomp), dim3(thr),
+                       2 * sizeof(cpx<T>) * C * K[a], p->stream, data, K[a], stride[a], ntot, sign,
+                       a == 2 ? packed : (T*)nullptr, C);
   }
 }
 

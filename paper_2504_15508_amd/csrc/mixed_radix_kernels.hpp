@@ -202,31 +202,23 @@ __device__ __forceinline__ cpx<T> unit_root(int a, int b, int sign) {
   return cpx<T>{c, sign > 0 ? s : -s};
 }
 
-// In-place unnormalised DFT of every length-N row along one axis:
-// X[k] = sum_n x[n] exp(sign 2 pi i n k / N).  Row r of component c starts
-// at c * comp_stride + (r / stride) * stride * N + r % stride and its
-// elements are stride apart (stride 1: x rows, Kx: y columns, Kx Ky: z
-// columns).  Grid (rows, components); LDS 2 N complex values.  With packed
-// != nullptr the real parts are written instead to packed[4 e + c] (e the
-// mesh index of the element, c the component): the last inverse pass leaves
-// the three fields interleaved for the gather.
-// Self-sorting stages: with p points already transformed, butterfly i
-// (0 <= i < N/R) takes x[i + q N/R], q < R, applies the twiddles
-// exp(sign 2 pi i q k / (p R)) with k = i mod p, a length-R DFT, and stores
-// to (i - k) R + k + s p, s < R.
+// One self-sorting stage on C rows of N points held in LDS (row c at c N).
 template <typename T, int R>
-__device__ __forceinline__ void stockham_stage(const cpx<T>* __restrict__ a, cpx<T>* __restrict__ b, int N, int p,
-                                               int sign) {
+__device__ __forceinline__ void stockham_stage(const cpx<T>* __restrict__ a, cpx<T>* __restrict__ b, int N, int C,
+                                               int p, int sign) {
   const int nb = N / R;
   cpx<T> w[R];
 #pragma unroll
   for (int t = 0; t < R; ++t) w[t] = unit_root<T>(t, R, sign);
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+  for (int it = threadIdx.x; it < C * nb; it += blockDim.x) {
+    const int c = it % C, i = it / C;
+    const cpx<T>* ar = a + c * N;
+    cpx<T>* br = b + c * N;
     const int k = i % p;
     cpx<T> u[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      u[q] = a[i + q * nb];
+      u[q] = ar[i + q * nb];
       if (q > 0 && k > 0) u[q] = cmul(u[q], unit_root<T>((q * k) % (p * R), p * R, sign));
     }
     const int j = (i - k) * R + k;
@@ -235,30 +227,50 @@ __device__ __forceinline__ void stockham_stage(const cpx<T>* __restrict__ a, cpx
       cpx<T> v = u[0];
 #pragma unroll
       for (int q = 1; q < R; ++q) v = cadd(v, cmul(u[q], w[(q * s2) % R]));
-      b[j + s2 * p] = v;
+      br[j + s2 * p] = v;
     }
   }
 }
 
+// In-place unnormalised DFT of every length-N row along one axis:
+// X[k] = sum_n x[n] exp(sign 2 pi i n k / N).  Row r of component c starts
+// at c * comp_stride + (r / stride) * stride * N + r % stride and its
+// elements are stride apart (stride 1: x rows, Kx: y columns, Kx Ky: z
+// columns).  Block b transforms the C consecutive rows b C .. b C + C - 1
+// (C divides stride, so they lie side by side in memory and a load of one
+// element of each is C contiguous values).  Grid (rows / C, components); LDS
+// 2 C N complex values.  With packed != nullptr the real parts are written
+// instead to packed[4 e + c] (e the mesh index of the element, c the
+// component): the last inverse pass leaves the three fields interleaved for
+// the gather.
+// Self-sorting stages: with p points already transformed, butterfly i
+// (0 <= i < N/R) takes x[i + q N/R], q < R, applies the twiddles
+// exp(sign 2 pi i q k / (p R)) with k = i mod p, a length-R DFT, and stores
+// to (i - k) R + k + s p, s < R.
 template <typename T>
 __global__ void __launch_bounds__(256) k_mixed_fft_axis(cpx<T>* __restrict__ data, int N, int64_t stride,
-                                                        int64_t comp_stride, int sign, T* __restrict__ packed) {
+                                                        int64_t comp_stride, int sign, T* __restrict__ packed,
+                                                        int C) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<T>* a = reinterpret_cast<cpx<T>*>(smem);
-  cpx<T>* b = a + N;
-  const int64_t r = blockIdx.x;
-  const int64_t rbase = (r / stride) * stride * N + (r % stride);
-  cpx<T>* row = data + (int64_t)blockIdx.y * comp_stride + rbase;
-  for (int e = threadIdx.x; e < N; e += blockDim.x) a[e] = row[(int64_t)e * stride];
+  cpx<T>* b = a + C * N;
+  const int64_t r0 = (int64_t)blockIdx.x * C;
+  // rows r0 .. r0 + C - 1 share r / stride, so row c starts at rbase + c
+  const int64_t rbase = (r0 / stride) * stride * N + (r0 % stride);
+  cpx<T>* base = data + (int64_t)blockIdx.y * comp_stride + rbase;
+  for (int t = threadIdx.x; t < C * N; t += blockDim.x) {
+    const int e = t / C, c = t - e * C;
+    a[c * N + e] = base[(int64_t)e * stride + c];
+  }
   __syncthreads();
   int p = 1, rem = N;
   while (rem > 1) {
     const int R = (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : (rem % 3 == 0) ? 3 : 5;
     switch (R) {
-      case 4: stockham_stage<T, 4>(a, b, N, p, sign); break;
-      case 2: stockham_stage<T, 2>(a, b, N, p, sign); break;
-      case 3: stockham_stage<T, 3>(a, b, N, p, sign); break;
-      default: stockham_stage<T, 5>(a, b, N, p, sign); break;
+      case 4: stockham_stage<T, 4>(a, b, N, C, p, sign); break;
+      case 2: stockham_stage<T, 2>(a, b, N, C, p, sign); break;
+      case 3: stockham_stage<T, 3>(a, b, N, C, p, sign); break;
+      default: stockham_stage<T, 5>(a, b, N, C, p, sign); break;
     }
     __syncthreads();
     cpx<T>* t = a;
@@ -267,10 +279,11 @@ __global__ void __launch_bounds__(256) k_mixed_fft_axis(cpx<T>* __restrict__ dat
     p *= R;
     rem /= R;
   }
-  if (packed) {
-    for (int e = threadIdx.x; e < N; e += blockDim.x) packed[4 * (rbase + (int64_t)e * stride) + blockIdx.y] = a[e].x;
-  } else {
-    for (int e = threadIdx.x; e < N; e += blockDim.x) row[(int64_t)e * stride] = a[e];
+  for (int t = threadIdx.x; t < C * N; t += blockDim.x) {
+    const int e = t / C, c = t - e * C;
+    const int64_t off = (int64_t)e * stride + c;
+    if (packed) packed[4 * (rbase + off) + blockIdx.y] = a[c * N + e].x;
+    else base[off] = a[c * N + e];
   }
 }
 
