@@ -209,3 +209,27 @@ def test_mixed_plan_debug_buffers(torch_dev):
     assert np.abs(G - G0[:7, :10, :7]).max() <= 1e-13 * np.abs(G0).max()
     with pytest.raises(ValueError, match="not available"):
         plan.debug_buffer(dl._lib.BUF_SPECTRUM)
+
+
+def test_int32_saturation_matches_oracle(torch_dev):
+    # at a scale of 2e9 every partial value above ~1.07 overflows int32 and
+    # clamps; the kernels must clamp exactly as the oracle does (a scale that
+    # is not a power of two, so that no exact half-quantum ties arise)
+    import paper_2504_15508_amd as dl
+    torch = torch_dev
+    s = small_water()
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    plan = dl.Plan((10, 15, 10), order=5, beta=BETA, coulomb_k=KE, precision="fp64", capacity=s.n)
+    plan.set_box(s.box)
+    plan.set_fft_int32((2, 3, 2), 2e9)
+    E, fi, fw, W = plan.compute(t(s.ion_pos), t(s.ion_q), t(s.wc_pos), t(s.wc_q))
+    torch.cuda.synchronize()
+    F = np.concatenate([fi.cpu().numpy(), fw.cpu().numpy()])
+    E0, F0, W0 = pppm.pppm_int32(s.all_pos(), s.all_q(), s.box, (10, 15, 10), 5, BETA, KE, (2, 3, 2), 2e9)
+    E1, F1, _ = pppm.pppm(s.all_pos(), s.all_q(), s.box, (10, 15, 10), 5, BETA, KE)
+    print(f"saturated int32: dE={abs(float(E) - E0) / abs(E0):.2e} dF={rel(F, F0):.2e} "
+          f"(vs exact transforms {rel(F0, F1):.2e})", flush=True)
+    assert rel(F0, F1) > 1e-3            # the clamp really changes the result
+    # agreement to the quantum's scale (5e-10: a value whose FP64 rounding in
+    # the two summation orders straddles a half-quantum moves by one quantum)
+    assert rel(F, F0) <= 1e-8 and abs(float(E) - E0) <= 1e-9 * abs(E0)
