@@ -69,7 +69,8 @@ constexpr int kMinMesh = 16;
 constexpr int kMaxMesh = 512;
 constexpr int kMaxOrder = 8;
 constexpr int kMinOrder = 2;
-constexpr int kMaxQ32Mesh = 256;  // int32-quantised transforms are direct sums, O(K) per output
+constexpr int kMaxQ32Mesh = 256;
+constexpr int64_t kMixedSplitMinParticles = 65536;  // split plane spread from this many particles  // int32-quantised transforms are direct sums, O(K) per output
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -158,6 +159,7 @@ struct dplr_lr_plan_s {
   size_t lds_mplane = 0;      // ... LDS of the plane spread (0: the plane does not fit; global atomics)
   void* mrec = nullptr;       // ... per-particle stencil offsets and charge (plane spread)
   int* mspk = nullptr;        // ... per-particle packed stencil starts (plane spread)
+  int msplit = 1;             // ... particle ranges per plane of the split plane spread (partials in mmesh)
   int q32_nodes[3] = {0, 0, 0};  // int32-quantised transforms: node blocks per axis (0: off)
   double q32_scale = 0.0;
   int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_ifftx = 256, thr_ixy = 256;
@@ -630,8 +632,14 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
       hipLaunchKernelGGL((k_mixed_prep<T, P>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                          (const T*)ion_pos, (const T*)ion_q, (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0],
                          ih[1], ih[2], g.K[0], g.K[1], g.K[2], (T4<T>*)p->mrec, p->mspk);
-    hipLaunchKernelGGL((k_mixed_spread_plane<T, P>), dim3(g.K[2]), dim3(1024), p->lds_mplane, s,
-                       (const T4<T>*)p->mrec, (const int*)p->mspk, n, g.K[0], g.K[1], g.K[2], spec);
+    // split the particles over S blocks per plane when the planes alone
+    // leave most compute units idle and there are enough particles
+    const int S = n >= kMixedSplitMinParticles ? p->msplit : 1;
+    hipLaunchKernelGGL((k_mixed_spread_plane<T, P>), dim3(g.K[2], S), dim3(1024), p->lds_mplane, s,
+                       (const T4<T>*)p->mrec, (const int*)p->mspk, n, g.K[0], g.K[1], g.K[2], spec, p->mmesh);
+    if (S > 1)
+      hipLaunchKernelGGL(k_mixed_combine<T>, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s,
+                         (const long long*)p->mmesh, S, ntot, spec);
   } else if (n > 0) {
     ProfScope ps(p, 11);
     hipLaunchKernelGGL((k_mixed_spread<T, P>), dim3(nbp), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
@@ -762,7 +770,12 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
     p->mblk = (int)((ntot + 255) / 256);
     dplr_lr_status sm = DPLR_LR_OK;
     void* tmp = nullptr;
-    if (sm == DPLR_LR_OK) { sm = alloc(p, &tmp, sizeof(long long) * ntot, "mixed-radix mesh"); p->mmesh = (long long*)tmp; }
+    // particle ranges per plane of the split plane spread: enough blocks for 256 CUs, at most 8
+    p->msplit = std::max(1, std::min(8, 256 / g.K[2]));
+    if (sm == DPLR_LR_OK) {
+      sm = alloc(p, &tmp, sizeof(long long) * ntot * p->msplit, "mixed-radix mesh (or split partial meshes)");
+      p->mmesh = (long long*)tmp;
+    }
     if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mspec, cs * ntot, "mixed-radix spectrum"); }
     if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mfield, 3 * cs * ntot, "mixed-radix field spectra"); }
     if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mpacked, 4 * ts * ntot, "mixed-radix fields"); }

@@ -114,24 +114,30 @@ __global__ void __launch_bounds__(256) k_mixed_prep(const T* __restrict__ ion_po
 // (in LDS) those whose stencil covers plane z, and once 1024 are queued (or
 // at the end) adds their P^2 plane terms with LDS integer atomics, so the
 // weight arithmetic runs on full waves.  Integer sums are exact and order
-// independent.  The plane is written as complex values (imaginary part 0)
-// into the spectrum buffer.  Grid Kz blocks of 1024 threads; LDS Kx Ky
-// 64-bit words.
+// independent.  Grid (Kz, S) blocks of 1024 threads: block (z, s) takes the
+// s-th of S consecutive particle ranges.  With S = 1 the plane is written as
+// complex values (imaginary part 0) into the spectrum buffer; with S > 1 as
+// 64-bit integers into partial[s][z][y][x], which k_mixed_combine adds.  LDS
+// Kx Ky 64-bit words.
 template <typename T, int P>
 __global__ void __launch_bounds__(1024) k_mixed_spread_plane(const T4<T>* __restrict__ rec,
                                                              const int* __restrict__ spk, int64_t n, int Kx, int Ky,
-                                                             int Kz, cpx<T>* __restrict__ spec) {
+                                                             int Kz, cpx<T>* __restrict__ spec,
+                                                             long long* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned long long pl[];
   __shared__ int queue[2048];
   __shared__ int qn;
   const int z = blockIdx.x;
   const int nxy = Kx * Ky;
+  const int S = gridDim.y;
+  const int64_t chunk = (n + S - 1) / S;
+  const int64_t lo = chunk * blockIdx.y, hi = min(n, lo + chunk);
   for (int e = threadIdx.x; e < nxy; e += blockDim.x) pl[e] = 0ull;
   if (threadIdx.x == 0) qn = 0;
   __syncthreads();
-  for (int64_t base = 0; base < n; base += blockDim.x) {
+  for (int64_t base = lo; base < hi; base += blockDim.x) {
     const int64_t i = base + threadIdx.x;
-    if (i < n) {
+    if (i < hi) {
       int tz = z - (spk[i] >> 20);
       if (tz < 0) tz += Kz;
       if (tz < P) queue[atomicAdd(&qn, 1)] = (int)i;
@@ -139,7 +145,7 @@ __global__ void __launch_bounds__(1024) k_mixed_spread_plane(const T4<T>* __rest
     __syncthreads();
     const int m = qn;  // < 2048: at most 1023 left over plus 1024 new
     __syncthreads();   // every thread has read qn before the next chunk adds to it
-    if (m >= (int)blockDim.x || base + blockDim.x >= n) {
+    if (m >= (int)blockDim.x || base + blockDim.x >= hi) {
       for (int k = threadIdx.x; k < m; k += blockDim.x) {
         const int j = queue[k];
         const T4<T> rc = rec[j];
@@ -175,9 +181,25 @@ __global__ void __launch_bounds__(1024) k_mixed_spread_plane(const T4<T>* __rest
     }
   }
   __syncthreads();
-  cpx<T>* out = spec + (int64_t)z * nxy;
-  for (int e = threadIdx.x; e < nxy; e += blockDim.x)
-    out[e] = cpx<T>{(T)((double)(long long)pl[e] * (1.0 / kMixedFixedScale)), (T)0};
+  if (S == 1) {
+    cpx<T>* out = spec + (int64_t)z * nxy;
+    for (int e = threadIdx.x; e < nxy; e += blockDim.x)
+      out[e] = cpx<T>{(T)((double)(long long)pl[e] * (1.0 / kMixedFixedScale)), (T)0};
+  } else {
+    long long* out = partial + ((int64_t)blockIdx.y * Kz + z) * nxy;
+    for (int e = threadIdx.x; e < nxy; e += blockDim.x) out[e] = (long long)pl[e];
+  }
+}
+
+// Sum of the S integer partial meshes of the split plane spread -> complex.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mixed_combine(const long long* __restrict__ partial, int S, int64_t ntot,
+                                                       cpx<T>* __restrict__ spec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  long long v = 0;
+  for (int s2 = 0; s2 < S; ++s2) v += partial[(int64_t)s2 * ntot + i];
+  spec[i] = cpx<T>{(T)((double)v * (1.0 / kMixedFixedScale)), (T)0};
 }
 
 // Fixed point -> complex mesh; clears the accumulators for the next call.

@@ -190,6 +190,14 @@ def test_int32_mode_switches_and_rejections(torch_dev):
         p2.set_fft_int32((2, 2, 2))
 
 
+def test_full_size_split_plane_spread(torch_dev):
+    # 288,768 charges on a mesh with 30 z planes: the plane spread splits the
+    # particles over 8 blocks per plane and adds the integer partial planes
+    w = systems.workload(3)
+    s = w.system()
+    check_vs_pppm(torch_dev, s, (60, 48, 30), 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
+
+
 def test_full_size_mixed_mesh_fp32(torch_dev):
     # the benchmark's 216,576 atoms + 72,192 WCs on a 120^3 mesh (the bench
     # leg's launch), element-wise against the oracle at the same mesh
