@@ -257,6 +257,36 @@ def overlap_leg(plan, step, W, K, n_atoms, energy, dev):
                                    f"{n_atoms} atoms"}
 
 
+def step_percentiles(plan, step, W, K, dev):
+    """Median, p10 and p90 of the per-frame step time: each of the K timed
+    frames captured in a graph of its own, replayed between HIP events (GPU
+    time of the step without host launch gaps)."""
+    import numpy as np
+    import torch
+
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        step(plan, 0)
+    torch.cuda.synchronize()
+    graphs = []
+    for t in range(W, W + K):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            step(plan, t)
+        graphs.append(g)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in graphs]
+    with torch.cuda.stream(stream):
+        for g, (a, b) in zip(graphs, ev):
+            a.record(stream)
+            g.replay()
+            b.record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    del graphs
+    return {"p10": float(np.percentile(ms, 10)), "median": float(np.median(ms)),
+            "p90": float(np.percentile(ms, 90)), "frames": int(K)}
+
+
 def mixed_leg(args, make_plan, step, timed_graph, timed_eager, s0, qi, qw, w, dev):
     """The mixed-radix kernels: the same 216,576 + 72,192 charges on a 120^3
     mesh (h = 1.078 A, next to the 128^3 of the headline), and the paper's
@@ -507,6 +537,10 @@ def main():
     else:
         log("timed region: graph replay")
         sec = timed_graph(lambda t: step(plan, t))
+    pct = None
+    if not args.eager_only:
+        log("per-frame graphs: step time percentiles")
+        pct = step_percentiles(plan, step, W, K, dev)
     log("eager pass with per-kernel HIP events")
     eager_sec, prof = timed_eager(plan, True)
     if sec is None:
@@ -589,6 +623,7 @@ def main():
                    "particles": N, "atoms": s0.n_ion, "wcs": s0.n_wc, "mesh": w.mesh, "order": args.order},
         "atoms_per_s": s0.n_ion / sec,
         "eager_ms_per_step": eager_sec * 1e3,
+        "step_ms_percentiles": pct,
         "step_alg_bytes": step_bytes,
         "step_roofline_frac": step_bytes / sec / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
