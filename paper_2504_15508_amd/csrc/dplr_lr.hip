@@ -663,8 +663,10 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
     ProfScope ps(p, 13);
     hipLaunchKernelGGL(k_mixed_poisson<T>, dim3((unsigned)p->mblk), dim3(256), 0, s, spec, field, p->G, g.K[0],
                        g.K[1], g.K[2], pc, q32 ? p->cfg.coulomb_k / V : 1.0, p->partials);
-    hipLaunchKernelGGL(k_mixed_reduce, dim3(1), dim3(256), 0, s, (const double*)p->partials, p->mblk,
-                       p->cfg.coulomb_k / (2.0 * V), energy, want_virial ? virial : (double*)nullptr);
+    // with particles, block 0 of the gather reduces the partials instead
+    if (n == 0)
+      hipLaunchKernelGGL(k_mixed_reduce, dim3(1), dim3(256), 0, s, (const double*)p->partials, p->mblk,
+                         p->cfg.coulomb_k / (2.0 * V), energy, want_virial ? virial : (double*)nullptr);
   }
   if (n > 0) {
     {
@@ -676,7 +678,8 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
     hipLaunchKernelGGL((k_mixed_gather<T, P>), dim3(nbg), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
                        (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], g.K[0], g.K[1], g.K[2],
                        (const T4<T>*)p->mpacked, (T*)ion_force, (T*)wc_force, q32 ? (T)1 : (T)(p->cfg.coulomb_k / V),
-                       (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0);
+                       (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0, (const double*)p->partials, p->mblk,
+                       p->cfg.coulomb_k / (2.0 * V), energy, want_virial ? virial : (double*)nullptr);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(p, e, "kernel launch");

@@ -421,7 +421,8 @@ __global__ void __launch_bounds__(256) k_mixed_reduce(const double* __restrict__
 }
 
 // F_ja = (k_e q_j / V) sum_g W(u_j - g) E_a(g), caller's order, from the
-// interleaved real fields (x, y, z, unused) the last inverse pass wrote.  Block of
+// interleaved real fields (x, y, z, unused) the last inverse pass wrote.
+// Block 0 also reduces the energy/virial partials (as k_mixed_reduce).  Block of
 // 256 threads: 256 / P particles, one thread per (particle, stencil plane tz);
 // the P plane sums of a particle are added in tz order (deterministic).
 template <typename T, int P>
@@ -430,8 +431,16 @@ __global__ void __launch_bounds__(256) k_mixed_gather(const T* __restrict__ ion_
                                                       int64_t n_ion, int64_t n, double ihx, double ihy, double ihz,
                                                       int Kx, int Ky, int Kz, const T4<T>* __restrict__ Ef,
                                                       T* __restrict__ ion_f, T* __restrict__ wc_f, T fscale,
-                                                      int accumulate) {
+                                                      int accumulate, const double* __restrict__ partials,
+                                                      int nblk, double pre, double* __restrict__ energy,
+                                                      double* __restrict__ virial) {
   __shared__ T part[256][3];
+  if (blockIdx.x == 0) {
+    // block 0 also finishes the energy and virial (the ik multiply's block
+    // partials are complete: that kernel ran before this one on the stream)
+    __shared__ double red[7 * 256];
+    reduce_partials(partials, nblk, pre, energy, virial, red);
+  }
   constexpr int PPB = 256 / P;
   const int jl = threadIdx.x / P, tz = threadIdx.x % P;
   const int64_t i = (int64_t)blockIdx.x * PPB + jl;
