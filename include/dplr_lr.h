@@ -124,7 +124,8 @@ dplr_lr_status dplr_lr_set_stream(dplr_lr_plan p, void* hip_stream);
  * field spectra carry k_e / V, so the inverse transforms produce the field
  * (eV/A per unit charge), values of order one.  nodes (host, 3 ints) must
  * divide the mesh sizes; scale in (0, 2^31].  nodes = NULL switches the mode
- * off.  Returns E_UNSUPPORTED on power-of-two plans.  Takes effect from the
+ * off.  Returns E_UNSUPPORTED on plans whose mesh runs on the plane/pencil
+ * kernels (powers of two from 16 to 512).  Takes effect from the
  * next compute; energy and virial come from the quantised charge spectrum. */
 dplr_lr_status dplr_lr_set_fft_int32(dplr_lr_plan p, const int32_t nodes[3], double scale);
 
