@@ -104,6 +104,8 @@ def test_null_plan_calls_fail_cleanly(lib):
     assert L.dplr_lr_compute_energy_forces_virial(None, 0, None, None, 0, None, None, None, None, None,
                                                   None) == lib.E_INVALID
     assert L.dplr_lr_plan_destroy(None) == lib.OK
+    nodes = (ctypes.c_int32 * 3)(2, 3, 2)
+    assert L.dplr_lr_set_fft_int32(None, nodes, 1e7) == lib.E_INVALID
     assert L.dplr_lr_workspace_bytes(None) == 0
     assert L.dplr_lr_profile_stage_name(3) == b"spread_fftx"
     assert L.dplr_lr_profile_stage_name(99) == b""
