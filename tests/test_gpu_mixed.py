@@ -39,7 +39,8 @@ def test_paper_grids(torch_dev, mesh, precision):
 # (160, 135, 8) and (240, 90, 10): xy planes too large for LDS, so the
 # spread takes the global-atomic kernel instead of the plane kernel
 @pytest.mark.parametrize("mesh,order", [((15, 25, 27), 3), ((45, 30, 20), 7), ((8, 8, 8), 5), ((9, 10, 6), 6),
-                                        ((6, 5, 4), 4), ((96, 80, 75), 5), ((160, 135, 8), 5), ((240, 90, 10), 4)])
+                                        ((6, 5, 4), 4), ((96, 80, 75), 5), ((160, 135, 8), 5), ((240, 90, 10), 4),
+                                        ((480, 18, 20), 5), ((12, 500, 9), 3)])
 def test_mixed_sizes_fp64(torch_dev, mesh, order):
     s = systems.water_box(512, 25.0, seed=20261129, name="water512_25A")
     s.box = np.array([25.0, 27.5, 23.0])
@@ -241,3 +242,21 @@ def test_int32_saturation_matches_oracle(torch_dev):
     # agreement to the quantum's scale (5e-10: a value whose FP64 rounding in
     # the two summation orders straddles a half-quantum moves by one quantum)
     assert rel(F, F0) <= 1e-8 and abs(float(E) - E0) <= 1e-9 * abs(E0)
+
+
+def test_int32_longest_rows(torch_dev):
+    # int32 transforms take rows up to 256 points: 240 points on 8 nodes
+    import paper_2504_15508_amd as dl
+    torch = torch_dev
+    s = small_water()
+    mesh, nodes = (240, 12, 10), (8, 2, 2)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    plan = dl.Plan(mesh, order=5, beta=BETA, coulomb_k=KE, precision="fp64", capacity=s.n)
+    plan.set_box(s.box)
+    plan.set_fft_int32(nodes, 1e7)
+    E, fi, fw, W = plan.compute(t(s.ion_pos), t(s.ion_q), t(s.wc_pos), t(s.wc_q))
+    torch.cuda.synchronize()
+    F = np.concatenate([fi.cpu().numpy(), fw.cpu().numpy()])
+    E0, F0, W0 = pppm.pppm_int32(s.all_pos(), s.all_q(), s.box, mesh, 5, BETA, KE, nodes, 1e7)
+    print(f"int32 {mesh} nodes {nodes}: dE={abs(float(E) - E0) / abs(E0):.2e} dF={rel(F, F0):.2e}", flush=True)
+    assert rel(F, F0) <= 1e-7 and abs(float(E) - E0) <= 1e-8 * abs(E0)
