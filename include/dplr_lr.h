@@ -158,6 +158,38 @@ dplr_lr_status dplr_lr_scale_grad(dplr_lr_plan p, const double* grad_energy,
                                   int64_t n_ion, const void* ion_force, void* ion_grad,
                                   int64_t n_wc, const void* wc_force, void* wc_grad);
 
+/* ------------------------------------------------------------------------
+ * The same step without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It needs no plan: cfg and box_len (host) describe what
+ * dplr_lr_plan_create and dplr_lr_set_box would (cfg->capacity is not used),
+ * and the arguments after them are those of
+ * dplr_lr_compute_energy_forces_virial, with the same meaning, layout and
+ * results; hip_stream is a hipStream_t (NULL = the null stream).
+ *
+ * Working memory is one library-owned device array of
+ * DPLR_LR_NOALLOC_SCRATCH_BYTES per GPU, held from the library's load until
+ * the process ends; the call allocates nothing.  A request that does not fit
+ * returns DPLR_LR_E_CAPACITY before any device work (the 128^3 FP32 mesh
+ * leaves room for about 2.5 million particles, 64^3 for about 5 million).
+ * Only power-of-two meshes from 16 to 512 are taken (E_UNSUPPORTED
+ * otherwise).  The first call on a device looks up the array's address and
+ * writes the FFT twiddle tables into it with synchronous copies, so a caller
+ * that captures graphs makes one call before capturing.  The influence table
+ * is recomputed only when the mesh, order, alias range, beta or box differ
+ * from the previous call on that device.
+ *
+ * Every call on a GPU shares that GPU's array and leaves its contents there:
+ * calls that overlap on one GPU (two host threads, or two streams whose work
+ * can run at the same time) race and give wrong results; serialise them.
+ * Errors are reported by dplr_lr_last_error(NULL). */
+#define DPLR_LR_NOALLOC_SCRATCH_BYTES (128LL << 20)
+dplr_lr_status dplr_lr_compute_noalloc(const dplr_lr_config* cfg, const double box_len[3],
+                                       int64_t n_ion, const void* ion_pos, const void* ion_q,
+                                       int64_t n_wc, const void* wc_pos, const void* wc_q,
+                                       void* ion_force, void* wc_force, double* energy, double* virial6,
+                                       void* hip_stream);
+
 /* Release the plan and its workspace (synchronises the plan's stream). NULL is accepted. */
 dplr_lr_status dplr_lr_plan_destroy(dplr_lr_plan p);
 

@@ -16,12 +16,14 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_UNSUPPORTED", 3: "E_NO_BOX", 4: "
 FP32, FP64 = 0, 1
 ACCUMULATE, NO_VIRIAL, DIFF_AD = 0x1, 0x2, 0x4
 BUF_SPECTRUM, BUF_INFLUENCE, BUF_FIELD_SPECTRA = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 128 << 20  # DPLR_LR_NOALLOC_SCRATCH_BYTES
 
 # every symbol include/dplr_lr.h declares
 EXPORTS = [
     "dplr_lr_abi_version", "dplr_lr_config_default", "dplr_lr_config_validate",
     "dplr_lr_plan_create", "dplr_lr_set_stream", "dplr_lr_set_fft_int32", "dplr_lr_set_box",
-    "dplr_lr_compute_energy_forces_virial", "dplr_lr_scale_grad", "dplr_lr_plan_destroy",
+    "dplr_lr_compute_energy_forces_virial", "dplr_lr_compute_noalloc", "dplr_lr_scale_grad",
+    "dplr_lr_plan_destroy",
     "dplr_lr_last_error", "dplr_lr_workspace_bytes", "dplr_lr_debug_copy", "dplr_lr_debug_size",
     "dplr_lr_profile_enable", "dplr_lr_profile_read", "dplr_lr_profile_stage_name",
     "dplr_lr_mlp_config_default", "dplr_lr_mlp_param_count", "dplr_lr_mlp_create", "dplr_lr_mlp_destroy",
@@ -83,6 +85,7 @@ def load():
         "dplr_lr_set_fft_int32": ([p, ctypes.POINTER(i32), d], ctypes.c_int),
         "dplr_lr_set_box": ([p, ctypes.POINTER(d)], ctypes.c_int),
         "dplr_lr_compute_energy_forces_virial": ([p, i64, p, p, i64, p, p, p, p, p, p], ctypes.c_int),
+        "dplr_lr_compute_noalloc": ([cfgp, ctypes.POINTER(d), i64, p, p, i64, p, p, p, p, p, p, p], ctypes.c_int),
         "dplr_lr_scale_grad": ([p, p, i64, p, p, i64, p, p], ctypes.c_int),
         "dplr_lr_plan_destroy": ([p], ctypes.c_int),
         "dplr_lr_last_error": ([p], ctypes.c_char_p),

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,7 +19,13 @@ using namespace dplr;
 
 namespace {
 
-thread_local std::string g_global_error;
+// Messages of failed calls.  Fixed buffers: recording an error allocates
+// nothing (the no-allocation entry point shares them).
+constexpr size_t kErrLen = 512;
+thread_local char g_global_error[kErrLen] = "";
+
+void set_msg(char* dst, const char* m) { std::snprintf(dst, kErrLen, "%s", m ? m : ""); }
+void set_global_error(const char* m) { set_msg(g_global_error, m); }
 
 #ifndef DPLR_SPREAD_MIN_THREADS
 #define DPLR_SPREAD_MIN_THREADS 256
@@ -98,7 +105,8 @@ int round_threads(long elems) {
   return (int)t;
 }
 
-dplr_lr_status validate(const dplr_lr_config* c, std::string& msg) {
+dplr_lr_status validate(const dplr_lr_config* c, const char*& msg) {
+  msg = "";
   if (!c) { msg = "config is NULL"; return DPLR_LR_E_INVALID; }
   for (int a = 0; a < 3; ++a) {
     if (c->mesh[a] <= 0) { msg = "mesh sizes must be positive"; return DPLR_LR_E_INVALID; }
@@ -182,7 +190,7 @@ struct dplr_lr_plan_s {
   void* twiddle = nullptr;
   int64_t ws_bytes = 0;
   std::vector<void*> allocs;
-  std::string err;
+  char err[kErrLen] = "";
   // instrumentation: HIP event pairs around each kernel of compute
   bool prof = false;
   struct ProfRec { int stage; hipEvent_t a, b; };
@@ -232,13 +240,14 @@ struct ProfScope {
   }
 };
 
-dplr_lr_status fail(dplr_lr_plan p, dplr_lr_status st, const std::string& m) {
-  if (p) p->err = m; else g_global_error = m;
+dplr_lr_status fail(dplr_lr_plan p, dplr_lr_status st, const char* m) {
+  set_msg(p ? p->err : g_global_error, m);
   return st;
 }
 
 dplr_lr_status hip_fail(dplr_lr_plan p, hipError_t e, const char* what) {
-  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  char m[kErrLen];
+  std::snprintf(m, sizeof(m), "%s: %s", what, hipGetErrorString(e));
   return fail(p, e == hipErrorOutOfMemory ? DPLR_LR_E_NOMEM : DPLR_LR_E_DEVICE, m);
 }
 
@@ -395,13 +404,31 @@ void free_all(dplr_lr_plan p) {
   p->allocs.clear();
 }
 
+// Raises a kernel's dynamic-LDS limit to at least `bytes`, never lowering a
+// limit that another plan set (all plans share the kernels).  Returns false
+// when the runtime refuses (the error is cleared).
+bool raise_lds_limit(const void* f, size_t bytes) {
+  static std::mutex mu;
+  static std::vector<std::pair<const void*, size_t>> set;
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto& e : set)
+    if (e.first == f && e.second >= bytes) return true;
+  if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  for (auto& e : set)
+    if (e.first == f) { e.second = bytes; return true; }
+  set.emplace_back(f, bytes);
+  return true;
+}
+
 template <typename T>
 void set_lds_attrs(dplr_lr_plan p) {
   // kernels whose dynamic LDS can exceed the 64 KiB default
   // a refusal is cleared here: a kernel that needed it then fails at its own launch
   auto attr = [&](const void* f, size_t b) {
-    if (b > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b) != hipSuccess)
-      (void)hipGetLastError();
+    if (b > 65536) (void)raise_lds_limit(f, b);
   };
   switch (p->cfg.order) {
 #define DPLR_ATTR(PP)                                                        \
@@ -713,6 +740,42 @@ dplr_lr_status dispatch_order(dplr_lr_plan p, int64_t n_ion, const void* a, cons
   return fail(p, DPLR_LR_E_UNSUPPORTED, "order");
 }
 
+// The per-call buffers of the plane/pencil path (everything but the twiddle
+// and influence tables), sized for `cap` particles, taken in a fixed order
+// from get(&ptr, bytes, what): hipMalloc for plans, consecutive pieces of the
+// static scratch array for the no-allocation entry point.
+template <typename Get>
+dplr_lr_status carve_workspace(dplr_lr_plan p, size_t cap, Get&& get) {
+  const Geo& g = p->geo;
+  const size_t ts = p->tsize, cs = 2 * ts;
+  const size_t nspec = (size_t)g.Kh * g.K[1] * g.K[2];
+  dplr_lr_status s2 = DPLR_LR_OK;
+#define DPLR_ALLOC(ptr, bytes, what)                                  \
+  if (s2 == DPLR_LR_OK) {                                             \
+    void* tmp__ = nullptr;                                            \
+    s2 = get(&tmp__, (bytes), what);                                  \
+    ptr = reinterpret_cast<decltype(ptr)>(tmp__);                     \
+  }
+  DPLR_ALLOC(p->bin_count, sizeof(int) * (g.nbins + 1), "bin_count");
+  DPLR_ALLOC(p->bin_start, sizeof(int) * (g.nbins + 1), "bin_start");
+  DPLR_ALLOC(p->bin_cursor, sizeof(int) * (g.nbins + 1), "bin_cursor");
+  p->block_hist = (size_t)g.nbins * sizeof(int) <= std::min<size_t>(p->lds_budget, 65536);
+  if (p->block_hist) DPLR_ALLOC(p->bin_hist, sizeof(int) * (size_t)p->max_chunks * g.nbins, "bin histograms");
+  DPLR_ALLOC(p->sorted, 4 * ts * cap, "sorted");
+  DPLR_ALLOC(p->perm, sizeof(int) * cap, "perm");
+  DPLR_ALLOC(p->sidx, sizeof(int) * cap, "stencil starts");
+  DPLR_ALLOC(p->spec, cs * nspec * g.nsplit, "spectrum (one partial per particle split)");
+  DPLR_ALLOC(p->qmax, sizeof(unsigned) * (size_t)std::max(p->max_chunks, 1), "charge maxima");
+  DPLR_ALLOC(p->fspec, 3 * cs * nspec, "field spectra");
+  // three interleaved field components, or (analytic differentiation) the
+  // potential in rows padded by kGatherAdPad
+  DPLR_ALLOC(p->field, ts * std::max<size_t>(3 * (size_t)g.K[0], (size_t)g.K[0] + kGatherAdPad) * g.K[1] * g.K[2],
+             "fields");
+  DPLR_ALLOC(p->partials, sizeof(double) * 8 * g.nzblk, "partials");
+#undef DPLR_ALLOC
+  return s2;
+}
+
 }  // namespace
 
 extern "C" {
@@ -733,11 +796,11 @@ void dplr_lr_config_default(dplr_lr_config* cfg) {
 }
 
 dplr_lr_status dplr_lr_config_validate(const dplr_lr_config* cfg, char* msg, int64_t msg_len) {
-  std::string m;
+  const char* m = "";
   dplr_lr_status st = validate(cfg, m);
-  if (st != DPLR_LR_OK) g_global_error = m;
+  if (st != DPLR_LR_OK) set_global_error(m);
   if (msg && msg_len > 0) {
-    std::snprintf(msg, (size_t)msg_len, "%s", m.c_str());
+    std::snprintf(msg, (size_t)msg_len, "%s", m);
   }
   return st;
 }
@@ -745,7 +808,7 @@ dplr_lr_status dplr_lr_config_validate(const dplr_lr_config* cfg, char* msg, int
 dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, dplr_lr_plan* out) {
   if (!out) return fail(nullptr, DPLR_LR_E_INVALID, "out is NULL");
   *out = nullptr;
-  std::string m;
+  const char* m = "";
   dplr_lr_status st = validate(cfg, m);
   if (st != DPLR_LR_OK) return fail(nullptr, st, m);
 
@@ -790,7 +853,7 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
       if (e2 != hipSuccess) sm = hip_fail(p, e2, "workspace init");
     }
     if (sm != DPLR_LR_OK) {
-      g_global_error = p->err;
+      set_global_error(p->err);
       free_all(p);
       delete p;
       return sm;
@@ -808,17 +871,14 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
 #undef DPLR_PLANE
       }
       p->lds_mplane = lp;
-      if (lp > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp) != hipSuccess) {
-        (void)hipGetLastError();
-        p->lds_mplane = 0;
-      }
+      if (lp > 65536 && !raise_lds_limit(f, lp)) p->lds_mplane = 0;
       const size_t capn = (size_t)std::max<int64_t>(cfg->capacity, 1);
       void* t2 = nullptr;
       dplr_lr_status sr = DPLR_LR_OK;
       if (p->lds_mplane) sr = alloc(p, &p->mrec, 4 * ts * capn, "mixed-radix stencil records");
       if (p->lds_mplane && sr == DPLR_LR_OK) { sr = alloc(p, &t2, sizeof(int) * capn, "mixed-radix stencil starts"); p->mspk = (int*)t2; }
       if (sr != DPLR_LR_OK) {
-        g_global_error = p->err;
+        set_global_error(p->err);
         free_all(p);
         delete p;
         return sr;
@@ -832,38 +892,18 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
     return fail(nullptr, DPLR_LR_E_UNSUPPORTED, "no tiling fits the device's LDS for this mesh/order/precision");
   }
   const Geo& g = p->geo;
-  const size_t ts = p->tsize, cs = 2 * ts;
-  const size_t cap = (size_t)std::max<int64_t>(cfg->capacity, 1);
-  const size_t nspec = (size_t)g.Kh * g.K[1] * g.K[2];
   const size_t ng = (size_t)g.Kh * (g.K[1] / 2 + 1) * (g.K[2] / 2 + 1);
-  dplr_lr_status s2 = DPLR_LR_OK;
-#define DPLR_ALLOC(ptr, bytes, what)                                  \
-  if (s2 == DPLR_LR_OK) {                                             \
-    void* tmp__ = nullptr;                                            \
-    s2 = alloc(p, &tmp__, (bytes), what);                             \
-    ptr = reinterpret_cast<decltype(ptr)>(tmp__);                     \
+  dplr_lr_status s2 = alloc(p, &p->twiddle, 2 * p->tsize * g.twN, "twiddles");
+  if (s2 == DPLR_LR_OK) {
+    void* t = nullptr;
+    s2 = alloc(p, &t, sizeof(double) * ng, "influence");
+    p->G = (double*)t;
   }
-  DPLR_ALLOC(p->bin_count, sizeof(int) * (g.nbins + 1), "bin_count");
-  DPLR_ALLOC(p->bin_start, sizeof(int) * (g.nbins + 1), "bin_start");
-  DPLR_ALLOC(p->bin_cursor, sizeof(int) * (g.nbins + 1), "bin_cursor");
-  p->block_hist = (size_t)g.nbins * sizeof(int) <= std::min<size_t>(p->lds_budget, 65536);
-  if (p->block_hist) DPLR_ALLOC(p->bin_hist, sizeof(int) * (size_t)p->max_chunks * g.nbins, "bin histograms");
-  DPLR_ALLOC(p->sorted, 4 * ts * cap, "sorted");
-  DPLR_ALLOC(p->perm, sizeof(int) * cap, "perm");
-  DPLR_ALLOC(p->sidx, sizeof(int) * cap, "stencil starts");
-  DPLR_ALLOC(p->spec, cs * nspec * g.nsplit, "spectrum (one partial per particle split)");
-  DPLR_ALLOC(p->qmax, sizeof(unsigned) * (size_t)std::max(p->max_chunks, 1), "charge maxima");
-  DPLR_ALLOC(p->fspec, 3 * cs * nspec, "field spectra");
-  // three interleaved field components, or (analytic differentiation) the
-  // potential in rows padded by kGatherAdPad
-  DPLR_ALLOC(p->field, ts * std::max<size_t>(3 * (size_t)g.K[0], (size_t)g.K[0] + kGatherAdPad) * g.K[1] * g.K[2],
-             "fields");
-  DPLR_ALLOC(p->G, sizeof(double) * ng, "influence");
-  DPLR_ALLOC(p->partials, sizeof(double) * 8 * g.nzblk, "partials");
-  DPLR_ALLOC(p->twiddle, cs * g.twN, "twiddles");
-#undef DPLR_ALLOC
+  if (s2 == DPLR_LR_OK)
+    s2 = carve_workspace(p, (size_t)std::max<int64_t>(cfg->capacity, 1),
+                         [p](void** ptr, size_t bytes, const char* what) { return alloc(p, ptr, bytes, what); });
   if (s2 != DPLR_LR_OK) {
-    g_global_error = p->err;
+    set_global_error(p->err);
     free_all(p);
     delete p;
     return s2;
@@ -1013,7 +1053,7 @@ const char* dplr_lr_profile_stage_name(int32_t i) {
 }
 
 const char* dplr_lr_last_error(dplr_lr_plan p) {
-  return p ? p->err.c_str() : g_global_error.c_str();
+  return p ? p->err : g_global_error;
 }
 
 int64_t dplr_lr_workspace_bytes(dplr_lr_plan p) { return p ? p->ws_bytes : 0; }
@@ -1059,6 +1099,200 @@ dplr_lr_status dplr_lr_debug_copy(dplr_lr_plan p, int32_t which, void* dst, int6
   hipError_t e = hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, p->stream);
   if (e != hipSuccess) return hip_fail(p, e, "debug copy");
   return DPLR_LR_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Step without device allocation (dplr_lr_compute_noalloc).  Its working
+// buffers live in one file-scope device array, `scratch`; each GPU the library
+// runs on holds its own copy from module load to process exit.  Host code
+// never passes the array's name to a kernel (in host code the name is a
+// host-side stand-in, not a device address): set-up looks up each device's
+// address of it once, with hipGetSymbolAddress, and every kernel argument,
+// fill and copy uses that address.
+//
+// Layout of each device's copy: [FP32 twiddle tables for N = 16 .. 512]
+// [FP64 twiddle tables] (written once, at set-up) [influence table of the
+// last box] [the per-call buffers of carve_workspace].
+// ----------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)DPLR_LR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kTwMin = kMinMesh, kTwMax = kMaxMesh;
+constexpr size_t kTwEntries = 2 * kTwMax - kTwMin;  // 16 + 32 + ... + 512
+// the table of size N (a power of two) starts at entry N - 16
+size_t tw_entry(int N) { return (size_t)N - kTwMin; }
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr size_t kTwF32Bytes = (kTwEntries * sizeof(cpx<float>) + 255) & ~(size_t)255;
+constexpr size_t kTwF64Bytes = (kTwEntries * sizeof(cpx<double>) + 255) & ~(size_t)255;
+constexpr size_t kScratchHead = kTwF32Bytes + kTwF64Bytes;
+
+struct NoallocDevice {
+  bool ready = false;
+  unsigned char* ptr = nullptr;  // this device's address of `scratch`
+  size_t lds_budget = 0;
+  // what the influence table in scratch was computed for
+  bool g_valid = false;
+  int K[3] = {0, 0, 0};
+  int order = 0, alias = 0;
+  double beta = 0.0, box[3] = {0, 0, 0};
+};
+constexpr int kMaxDevices = 64;
+NoallocDevice g_noalloc[kMaxDevices];
+std::mutex g_noalloc_mu;
+
+template <typename T>
+void twiddle_tables(cpx<T>* w) {
+  for (int N = kTwMin; N <= kTwMax; N *= 2) {
+    cpx<T>* t = w + tw_entry(N);
+    for (int k = 0; k < N; ++k) {  // the values fill_twiddles gives plans
+      const double th = -2.0 * M_PI * (double)k / (double)N;
+      t[k].x = (T)std::cos(th);
+      t[k].y = (T)std::sin(th);
+    }
+  }
+}
+
+// Once per device, with that device current: the device address of scratch
+// and the twiddle tables (synchronous copies from host stack memory).
+dplr_lr_status noalloc_setup(int dev, NoallocDevice& d) {
+  if (d.ready) return DPLR_LR_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_fail(nullptr, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+  int lds = 0;
+  e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipDeviceGetAttribute");
+  cpx<float> tf[kTwEntries];
+  cpx<double> td[kTwEntries];
+  twiddle_tables<float>(tf);
+  twiddle_tables<double>(td);
+  unsigned char* base = (unsigned char*)ptr;
+  e = hipMemcpy(base, tf, sizeof(tf), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(base + kTwF32Bytes, td, sizeof(td), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "scratch set-up");
+  d.ptr = base;
+  d.lds_budget = (size_t)std::min(lds, 160 * 1024);
+  d.ready = true;
+  return DPLR_LR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dplr_lr_status dplr_lr_compute_noalloc(const dplr_lr_config* cfg, const double box_len[3], int64_t n_ion,
+                                       const void* ion_pos, const void* ion_q, int64_t n_wc, const void* wc_pos,
+                                       const void* wc_q, void* ion_force, void* wc_force, double* energy,
+                                       double* virial6, void* hip_stream) {
+  if (!cfg) return fail(nullptr, DPLR_LR_E_INVALID, "config is NULL");
+  dplr_lr_config cf = *cfg;
+  cf.capacity = 0;  // not used: the call's particle count sizes the buffers
+  cfg = &cf;
+  const char* m = "";
+  dplr_lr_status st = validate(cfg, m);
+  if (st != DPLR_LR_OK) return fail(nullptr, st, m);
+  if (!tuned_mesh(cfg->mesh))
+    return fail(nullptr, DPLR_LR_E_UNSUPPORTED, "the no-allocation step takes power-of-two meshes of 16 to 512 points");
+  if (!box_len) return fail(nullptr, DPLR_LR_E_INVALID, "box_len is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!(box_len[a] > 0.0) || !std::isfinite(box_len[a]))
+      return fail(nullptr, DPLR_LR_E_INVALID, "box lengths must be positive and finite");
+  if (n_ion < 0 || n_wc < 0) return fail(nullptr, DPLR_LR_E_INVALID, "negative particle count");
+  if (n_ion + n_wc > 0x7fffffffLL) return fail(nullptr, DPLR_LR_E_CAPACITY, "more than 2^31 - 1 particles");
+  if (n_ion > 0 && (!ion_pos || !ion_q || !ion_force)) return fail(nullptr, DPLR_LR_E_INVALID, "ion pointer is NULL");
+  if (n_wc > 0 && (!wc_pos || !wc_q || !wc_force)) return fail(nullptr, DPLR_LR_E_INVALID, "wc pointer is NULL");
+  if (!energy) return fail(nullptr, DPLR_LR_E_INVALID, "energy is NULL");
+  if (!virial6 && !(cfg->flags & DPLR_LR_NO_VIRIAL)) return fail(nullptr, DPLR_LR_E_INVALID, "virial6 is NULL");
+
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, DPLR_LR_E_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  NoallocDevice& d = g_noalloc[dev];
+  if ((st = noalloc_setup(dev, d)) != DPLR_LR_OK) return st;
+
+  // a plan on the host stack whose buffers are pieces of scratch
+  dplr_lr_plan_s pl;
+  dplr_lr_plan p = &pl;
+  p->cfg = *cfg;
+  p->cfg.capacity = n_ion + n_wc;
+  p->stream = (hipStream_t)hip_stream;
+  p->device = dev;
+  p->fp64 = cfg->precision == DPLR_LR_FP64;
+  p->tsize = p->fp64 ? sizeof(double) : sizeof(float);
+  p->lds_budget = d.lds_budget;
+  if (!choose_geometry(p))
+    return fail(nullptr, DPLR_LR_E_UNSUPPORTED, "no tiling fits the device's LDS for this mesh/order/precision");
+  const Geo& g = p->geo;
+  const size_t ng = (size_t)g.Kh * (g.K[1] / 2 + 1) * (g.K[2] / 2 + 1);
+  const size_t g_off = kScratchHead;
+  size_t off = align256(g_off + sizeof(double) * ng);
+  const size_t cap = (size_t)std::max<int64_t>(n_ion + n_wc, 1);
+  // sizes first: reject before touching the device
+  {
+    size_t need = off;
+    dplr_lr_plan_s dry;
+    dry.cfg = p->cfg; dry.fp64 = p->fp64; dry.tsize = p->tsize; dry.lds_budget = p->lds_budget; dry.geo = p->geo;
+    (void)carve_workspace(&dry, cap, [&need](void** ptr, size_t bytes, const char*) {
+      *ptr = nullptr;
+      need = align256(need + std::max<size_t>(bytes, 16));
+      return DPLR_LR_OK;
+    });
+    if (need > kScratchBytes) {
+      char msg[kErrLen];
+      std::snprintf(msg, sizeof(msg),
+                    "the no-allocation step needs %zu bytes of scratch for this mesh and %lld particles; "
+                    "it has %zu (DPLR_LR_NOALLOC_SCRATCH_BYTES)",
+                    need, (long long)(n_ion + n_wc), kScratchBytes);
+      return fail(nullptr, DPLR_LR_E_CAPACITY, msg);
+    }
+  }
+  p->twiddle = d.ptr + (p->fp64 ? kTwF32Bytes + sizeof(cpx<double>) * tw_entry(g.twN)
+                                : sizeof(cpx<float>) * tw_entry(g.twN));
+  p->G = reinterpret_cast<double*>(d.ptr + g_off);
+  (void)carve_workspace(p, cap, [&](void** ptr, size_t bytes, const char*) {
+    *ptr = d.ptr + off;
+    off = align256(off + std::max<size_t>(bytes, 16));
+    return DPLR_LR_OK;
+  });
+  // kernels with more than 64 KiB of dynamic LDS (limits are only ever raised)
+  if (p->fp64) set_lds_attrs<double>(p); else set_lds_attrs<float>(p);
+  // the influence table is kept from the last call on this device when the
+  // mesh, order, alias range, beta and box are the same
+  const bool same_g = d.g_valid && d.K[0] == g.K[0] && d.K[1] == g.K[1] && d.K[2] == g.K[2] &&
+                      d.order == cfg->order && d.alias == cfg->alias_range && d.beta == cfg->beta &&
+                      d.box[0] == box_len[0] && d.box[1] == box_len[1] && d.box[2] == box_len[2];
+  for (int a = 0; a < 3; ++a) p->box[a] = box_len[a];
+  p->has_box = true;
+  if (!same_g) {
+    d.g_valid = false;
+    hipLaunchKernelGGL(k_influence, dim3((unsigned)((ng + 127) / 128)), dim3(128), 0, p->stream, p->G, g, p->box[0],
+                       p->box[1], p->box[2], cfg->beta, cfg->order, cfg->alias_range);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(nullptr, e, "influence launch");
+    d.g_valid = true;
+    for (int a = 0; a < 3; ++a) { d.K[a] = g.K[a]; d.box[a] = box_len[a]; }
+    d.order = cfg->order;
+    d.alias = cfg->alias_range;
+    d.beta = cfg->beta;
+  }
+  // the global-atomic sort counts into bin_count, which must start at zero
+  // (scratch keeps the previous call's contents); a fill kernel, not a memset
+  if (!p->block_hist) {
+    hipLaunchKernelGGL(k_fill_int, dim3((g.nbins + 1 + 255) / 256), dim3(256), 0, p->stream, p->bin_count,
+                       g.nbins + 1, 0);
+  }
+  st = p->fp64 ? dispatch_order<double>(p, n_ion, ion_pos, ion_q, n_wc, wc_pos, wc_q, ion_force, wc_force, energy,
+                                        virial6)
+               : dispatch_order<float>(p, n_ion, ion_pos, ion_q, n_wc, wc_pos, wc_q, ion_force, wc_force, energy,
+                                       virial6);
+  if (st != DPLR_LR_OK) set_global_error(p->err);
+  return st;
 }
 
 }  // extern "C"

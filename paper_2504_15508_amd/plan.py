@@ -185,3 +185,58 @@ class Plan:
         if which == _lib.BUF_SPECTRUM:
             return c.view(kh, kz, ky)
         return c.view(3, kh, kz, ky)
+
+
+def compute_noalloc(mesh, box, ion_pos, ion_q, wc_pos=None, wc_q=None, order: int = 5, beta: float = 0.4,
+                    coulomb_k: float = 14.399645, alias_range: int = 2, flags: int = 0, diff: str = "ik",
+                    ion_force=None, wc_force=None, energy=None, virial=None):
+    """The step through dplr_lr_compute_noalloc: no plan, and no device
+    allocation inside the library (its working memory is a fixed device
+    array of NOALLOC_SCRATCH_BYTES per GPU).  Precision follows the dtype of
+    ion_pos (float32 or float64).  Output tensors that are not given are
+    allocated here by PyTorch.  Returns (energy, ion_force, wc_force, virial)."""
+    lib = _lib.load()
+    dt = ion_pos.dtype
+    if dt not in (torch.float32, torch.float64):
+        raise ValueError("positions must be float32 or float64")
+    dev = ion_pos.device
+    if diff not in ("ik", "ad"):
+        raise ValueError("diff must be 'ik' or 'ad'")
+    if diff == "ad":
+        flags = int(flags) | _lib.DIFF_AD
+    if isinstance(mesh, int):
+        mesh = (mesh, mesh, mesh)
+
+    def inp(t, cols):
+        if t is None:
+            return torch.empty((0, cols) if cols else (0,), dtype=dt, device=dev)
+        if t.device != dev or t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"inputs must be contiguous {dt} tensors on {dev}")
+        return t
+
+    ion_pos, ion_q, wc_pos, wc_q = inp(ion_pos, 3), inp(ion_q, 0), inp(wc_pos, 3), inp(wc_q, 0)
+    n_ion, n_wc = ion_pos.shape[0], wc_pos.shape[0]
+    if ion_q.shape[0] != n_ion or wc_q.shape[0] != n_wc:
+        raise ValueError("charge and position counts differ")
+    cfg = _lib.Config()
+    lib.dplr_lr_config_default(ctypes.byref(cfg))
+    cfg.mesh[:] = [int(m) for m in mesh]
+    cfg.order, cfg.beta, cfg.coulomb_k = int(order), float(beta), float(coulomb_k)
+    cfg.precision = _lib.FP64 if dt == torch.float64 else _lib.FP32
+    cfg.alias_range, cfg.flags = int(alias_range), int(flags)
+    if ion_force is None:
+        ion_force = torch.empty((n_ion, 3), dtype=dt, device=dev)
+    if wc_force is None:
+        wc_force = torch.empty((n_wc, 3), dtype=dt, device=dev)
+    if energy is None:
+        energy = torch.empty((), dtype=torch.float64, device=dev)
+    if virial is None:
+        virial = torch.empty(6, dtype=torch.float64, device=dev)
+    boxa = (ctypes.c_double * 3)(*[float(b) for b in box])
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        _lib.check(lib.dplr_lr_compute_noalloc(
+            ctypes.byref(cfg), boxa, n_ion, _ptr(ion_pos), _ptr(ion_q), n_wc, _ptr(wc_pos), _ptr(wc_q),
+            _ptr(ion_force), _ptr(wc_force), ctypes.c_void_p(energy.data_ptr()),
+            ctypes.c_void_p(virial.data_ptr()), ctypes.c_void_p(stream)))
+    return energy, ion_force, wc_force, virial
