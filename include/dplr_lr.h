@@ -139,9 +139,10 @@ dplr_lr_status dplr_lr_set_box(dplr_lr_plan p, const double box_len[3]);
 /* The long-range step.  Device inputs: ion_pos [n_ion][3], ion_q [n_ion],
  * wc_pos [n_wc][3], wc_q [n_wc] (plan precision).  Device outputs:
  * ion_force [n_ion][3] and wc_force [n_wc][3] (F = -dE/dr, eV/A, plan
- * precision), energy (1 double, eV) and virial6 (6 doubles, eV; may be NULL,
- * and must be NULL-tolerant only when the plan has DPLR_LR_NO_VIRIAL).
- * Pointers of an empty set (n = 0) may be NULL.  Requires set_box first and
+ * precision), energy (1 double, eV) and virial6 (6 doubles, eV).  Without
+ * DPLR_LR_NO_VIRIAL, virial6 must not be NULL (E_INVALID); with it the virial
+ * is not computed, virial6 is not written and may be NULL.  Pointers of an
+ * empty set (n = 0) may be NULL.  Requires set_box first and
  * n_ion + n_wc <= capacity. */
 dplr_lr_status dplr_lr_compute_energy_forces_virial(
     dplr_lr_plan p,
