@@ -221,8 +221,24 @@ int64_t dplr_lr_workspace_bytes(dplr_lr_plan p);
 #define DPLR_LR_BUF_SPECTRUM 0
 #define DPLR_LR_BUF_INFLUENCE 1
 #define DPLR_LR_BUF_FIELD_SPECTRA 2
+/* Mixed-radix plans: the number of partial values (real and imaginary parts
+ * counted separately) that the int32-quantised transforms of the last compute
+ * clamped to the int32 range, one uint64.  A partial value saturates when
+ * |value| * scale >= 2^31, i.e. above about 214.7 at the paper's scale 1e7
+ * (charge units in the forward transform, eV/A per unit charge in the
+ * inverse ones); a non-zero count means the forces of that call are not the
+ * rounded transforms of the header's dplr_lr_set_fft_int32 description. */
+#define DPLR_LR_BUF_Q32_CLAMPED 3
 dplr_lr_status dplr_lr_debug_copy(dplr_lr_plan p, int32_t which, void* dst, int64_t bytes);
 int64_t dplr_lr_debug_size(dplr_lr_plan p, int32_t which);
+
+/* One axis of the int32-quantised transform of dplr_lr_set_fft_int32 (for
+ * element-wise kernel tests): transforms, in place on the plan's stream, the
+ * device array data of ncomp (1..3) complex meshes [ncomp][Kz][Ky][Kx] (plan
+ * precision, x fastest) along axis (0 = x, 1 = y, 2 = z) with exp(sign 2 pi
+ * i n k / K_axis), sign = -1 or +1, using the plan's node counts and scale.
+ * E_UNSUPPORTED unless int32 transforms are enabled on a mixed-radix plan. */
+dplr_lr_status dplr_lr_debug_dft_q32(dplr_lr_plan p, int32_t axis, int32_t sign, void* data, int32_t ncomp);
 
 /* Instrumentation (not part of the method).  When enabled, compute records a
  * HIP event pair on the plan's stream around each of its kernels.

@@ -135,25 +135,30 @@ def forward(params, T, D, q, mu, inv_sigma, s_out, emulate_bf16=False):
     return dF, cache
 
 
-def loss_and_grad(params, cache, dF, target):
+def loss_and_grad(params, cache, dF, target, emulate_bf16=False):
     """Mean-squared loss and its gradients with respect to every parameter,
-    by the chain rule written out layer by layer."""
+    by the chain rule written out layer by layer.  With emulate_bf16 the
+    gradient at each layer output (dL/dc, then dL/dz3, dL/dz2, dL/dz1) is
+    rounded to bfloat16 before it is used, where the GPU backward rounds it
+    for its matrix products; pass the cache of forward(..., emulate_bf16=True)
+    so that activations and weights carry the forward's rounding too."""
+    r = bf16 if emulate_bf16 else (lambda a: a)
     n = dF.shape[0]
     diff = dF - target
     loss = float((diff * diff).mean())
     g = 2.0 * diff / (3 * n)                                   # dL/d dF
-    dc = cache["s_out"] * cache["q"][:, None] * np.einsum("na,nka->nk", g, cache["T"][:, :, 1:])
+    dc = r(cache["s_out"] * cache["q"][:, None] * np.einsum("na,nka->nk", g, cache["T"][:, :, 1:]))
     W = cache["W"]
     grads = {}
     grads["W4"] = cache["h3"].T @ dc
     grads["b4"] = dc.sum(0)
-    dz3 = (dc @ W[3].T) * dsilu(cache["z3"])
+    dz3 = r((dc @ W[3].T) * dsilu(cache["z3"]))
     grads["W3"] = cache["h2"].T @ dz3
     grads["b3"] = dz3.sum(0)
-    dz2 = (dz3 @ W[2].T) * dsilu(cache["z2"])
+    dz2 = r((dz3 @ W[2].T) * dsilu(cache["z2"]))
     grads["W2"] = cache["h1"].T @ dz2
     grads["b2"] = dz2.sum(0)
-    dz1 = (dz2 @ W[1].T) * dsilu(cache["z1"])
+    dz1 = r((dz2 @ W[1].T) * dsilu(cache["z1"]))
     grads["W1"] = cache["x"].T @ dz1
     grads["b1"] = dz1.sum(0)
     return loss, grads

@@ -257,7 +257,7 @@ def pppm_ad(pos, q, box, K, p: int, beta: float, ke: float, alias: int = 2, G=No
     return E, F, W
 
 
-def dft_axis_int32(x, axis: int, nodes: int, scale: float, sign: int):
+def dft_axis_int32(x, axis: int, nodes: int, scale: float, sign: int, return_partials: bool = False):
     """Unnormalised DFT along one axis as the paper's hardware-offloaded FFT
     forms it (Optimization section, reduction chains and int32 quantisation):
     the K points of the axis belong to `nodes` consecutive blocks of K/nodes
@@ -265,7 +265,10 @@ def dft_axis_int32(x, axis: int, nodes: int, scale: float, sign: int):
         P_b[k] = sum_{n in block b} x[n] exp(sign 2 pi i n k / K),
     whose real and imaginary parts are scaled by `scale`, rounded to the
     nearest integer and clamped to the int32 range; the integers are summed
-    over the blocks (exactly) and the sum is divided by `scale`."""
+    over the blocks (exactly) and the sum is divided by `scale`.
+    With return_partials the unrounded scaled partial values P_b * scale are
+    returned too, as an array [nodes, ...] in the axis-last layout of x with
+    the axis moved to the end."""
     x = np.asarray(x, dtype=np.complex128)
     K = x.shape[axis]
     if nodes < 1 or K % nodes:
@@ -276,14 +279,19 @@ def dft_axis_int32(x, axis: int, nodes: int, scale: float, sign: int):
     lo, hi = -2.0 ** 31, 2.0 ** 31 - 1
     acc_re = np.zeros(xm.shape, dtype=np.int64)
     acc_im = np.zeros(xm.shape, dtype=np.int64)
+    parts = []
     for b in range(nodes):
         n = np.arange(b * seg, (b + 1) * seg)
         w = np.exp(sign * 2j * math.pi * (np.outer(n, k) % K) / K)
         P = xm[..., n] @ w
         acc_re += np.clip(np.rint(P.real * scale), lo, hi).astype(np.int64)
         acc_im += np.clip(np.rint(P.imag * scale), lo, hi).astype(np.int64)
-    out = (acc_re.astype(np.float64) + 1j * acc_im.astype(np.float64)) / scale
-    return np.moveaxis(out, -1, axis)
+        if return_partials:
+            parts.append(P * scale)
+    out = np.moveaxis((acc_re.astype(np.float64) + 1j * acc_im.astype(np.float64)) / scale, -1, axis)
+    if return_partials:
+        return out, np.stack(parts)
+    return out
 
 
 def pppm_int32(pos, q, box, K, p: int, beta: float, ke: float, nodes, scale: float = 1e7,

@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_UNSUPPORTED", 3: "E_NO_BOX", 4: "
                 5: "E_DEVICE", 6: "E_NOMEM"}
 FP32, FP64 = 0, 1
 ACCUMULATE, NO_VIRIAL, DIFF_AD = 0x1, 0x2, 0x4
-BUF_SPECTRUM, BUF_INFLUENCE, BUF_FIELD_SPECTRA = 0, 1, 2
+BUF_SPECTRUM, BUF_INFLUENCE, BUF_FIELD_SPECTRA, BUF_Q32_CLAMPED = 0, 1, 2, 3
 NOALLOC_SCRATCH_BYTES = 128 << 20  # DPLR_LR_NOALLOC_SCRATCH_BYTES
 
 # every symbol include/dplr_lr.h declares
@@ -25,6 +25,7 @@ EXPORTS = [
     "dplr_lr_compute_energy_forces_virial", "dplr_lr_compute_noalloc", "dplr_lr_scale_grad",
     "dplr_lr_plan_destroy",
     "dplr_lr_last_error", "dplr_lr_workspace_bytes", "dplr_lr_debug_copy", "dplr_lr_debug_size",
+    "dplr_lr_debug_dft_q32",
     "dplr_lr_profile_enable", "dplr_lr_profile_read", "dplr_lr_profile_stage_name",
     "dplr_lr_mlp_config_default", "dplr_lr_mlp_param_count", "dplr_lr_mlp_create", "dplr_lr_mlp_destroy",
     "dplr_lr_mlp_set_stream", "dplr_lr_mlp_set_params", "dplr_lr_mlp_get_params", "dplr_lr_mlp_forward",
@@ -92,6 +93,7 @@ def load():
         "dplr_lr_workspace_bytes": ([p], i64),
         "dplr_lr_debug_copy": ([p, i32, p, i64], ctypes.c_int),
         "dplr_lr_debug_size": ([p, i32], i64),
+        "dplr_lr_debug_dft_q32": ([p, i32, i32, p, i32], ctypes.c_int),
         "dplr_lr_profile_enable": ([p, i32], ctypes.c_int),
         "dplr_lr_profile_read": ([p, p, p, i32, p, i32], ctypes.c_int),
         "dplr_lr_profile_stage_name": ([i32], ctypes.c_char_p),

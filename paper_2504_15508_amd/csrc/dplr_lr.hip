@@ -170,6 +170,7 @@ struct dplr_lr_plan_s {
   int msplit = 1;             // ... particle ranges per plane of the split plane spread (partials in mmesh)
   int q32_nodes[3] = {0, 0, 0};  // int32-quantised transforms: node blocks per axis (0: off)
   double q32_scale = 0.0;
+  unsigned long long* q32_clamped = nullptr;  // saturated partial values of the last compute
   int thr_spread = 256, thr_ffty = 256, thr_z = 256, thr_ifftx = 256, thr_ixy = 256;
   // device workspace
   int* bin_count = nullptr;
@@ -631,7 +632,7 @@ void launch_mixed_dft_q32(dplr_lr_plan p, cpx<T>* data, int ncomp, int sign, T* 
     const int64_t rows = ntot / K[a];
     hipLaunchKernelGGL(k_mixed_dft_q32<T>, dim3((unsigned)rows, (unsigned)ncomp), dim3(64), sizeof(cpx<T>) * K[a],
                        p->stream, data, K[a], stride[a], ntot, sign, p->q32_nodes[a], p->q32_scale,
-                       a == 2 ? packed : (T*)nullptr);
+                       a == 2 ? packed : (T*)nullptr, p->q32_clamped);
   }
 }
 
@@ -672,6 +673,10 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
     hipLaunchKernelGGL((k_mixed_spread<T, P>), dim3(nbp), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
                        (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], g.K[0], g.K[1], g.K[2],
                        (unsigned long long*)p->mmesh);
+  }
+  if (q32) {
+    // the saturation count of this call starts at zero (a fill kernel, not a memset)
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(p->q32_clamped), 2, 0);
   }
   {
     ProfScope ps(p, 12);
@@ -848,8 +853,13 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
     if (sm == DPLR_LR_OK) { sm = alloc(p, &tmp, sizeof(double) * ng, "influence"); p->G = (double*)tmp; }
     if (sm == DPLR_LR_OK) { sm = alloc(p, &tmp, sizeof(double) * 8 * p->mblk, "partials"); p->partials = (double*)tmp; }
     if (sm == DPLR_LR_OK) {
+      sm = alloc(p, &tmp, sizeof(unsigned long long), "int32 saturation count");
+      p->q32_clamped = (unsigned long long*)tmp;
+    }
+    if (sm == DPLR_LR_OK) {
       hipError_t e2 = hipMemset(p->mmesh, 0, sizeof(long long) * ntot);
       if (e2 == hipSuccess) e2 = hipMemset(p->G, 0, sizeof(double) * ng);
+      if (e2 == hipSuccess) e2 = hipMemset(p->q32_clamped, 0, sizeof(unsigned long long));
       if (e2 != hipSuccess) sm = hip_fail(p, e2, "workspace init");
     }
     if (sm != DPLR_LR_OK) {
@@ -1063,6 +1073,7 @@ int64_t dplr_lr_debug_size(dplr_lr_plan p, int32_t which) {
   const Geo& g = p->geo;
   const size_t cs = 2 * p->tsize;
   const size_t nspec = (size_t)g.Kh * g.K[1] * g.K[2];
+  if (which == DPLR_LR_BUF_Q32_CLAMPED) return p->mixed ? (int64_t)sizeof(unsigned long long) : -1;
   if (p->mixed && which != DPLR_LR_BUF_INFLUENCE) return -1;
   switch (which) {
     case DPLR_LR_BUF_SPECTRUM: return (int64_t)(cs * nspec);
@@ -1077,7 +1088,10 @@ dplr_lr_status dplr_lr_debug_copy(dplr_lr_plan p, int32_t which, void* dst, int6
   const int64_t size = dplr_lr_debug_size(p, which);
   if (size < 0) return fail(p, DPLR_LR_E_INVALID, "unknown buffer");
   if (!dst || bytes < 0 || bytes > size) return fail(p, DPLR_LR_E_INVALID, "bad destination or size");
-  const void* src = which == DPLR_LR_BUF_SPECTRUM ? p->spec : which == DPLR_LR_BUF_INFLUENCE ? (const void*)p->G : p->fspec;
+  const void* src = which == DPLR_LR_BUF_SPECTRUM    ? p->spec
+                    : which == DPLR_LR_BUF_INFLUENCE ? (const void*)p->G
+                    : which == DPLR_LR_BUF_Q32_CLAMPED ? (const void*)p->q32_clamped
+                                                      : p->fspec;
   if (which == DPLR_LR_BUF_SPECTRUM && p->plane && p->geo.nsplit > 1) {
     // the plane spread leaves one partial spectrum per particle split: report their sum
     const size_t cs = 2 * p->tsize;
@@ -1098,6 +1112,29 @@ dplr_lr_status dplr_lr_debug_copy(dplr_lr_plan p, int32_t which, void* dst, int6
   }
   hipError_t e = hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, p->stream);
   if (e != hipSuccess) return hip_fail(p, e, "debug copy");
+  return DPLR_LR_OK;
+}
+
+dplr_lr_status dplr_lr_debug_dft_q32(dplr_lr_plan p, int32_t axis, int32_t sign, void* data, int32_t ncomp) {
+  if (!p) return fail(nullptr, DPLR_LR_E_INVALID, "plan is NULL");
+  if (!p->mixed || p->q32_nodes[0] <= 0) return fail(p, DPLR_LR_E_UNSUPPORTED, "int32 transforms are not enabled on this plan");
+  if (axis < 0 || axis > 2 || (sign != 1 && sign != -1) || ncomp < 1 || ncomp > 3 || !data)
+    return fail(p, DPLR_LR_E_INVALID, "axis in 0..2, sign +-1, ncomp in 1..3, data not NULL");
+  const int K[3] = {p->geo.K[0], p->geo.K[1], p->geo.K[2]};
+  const int64_t ntot = (int64_t)K[0] * K[1] * K[2];
+  const int64_t stride[3] = {1, K[0], (int64_t)K[0] * K[1]};
+  const int64_t rows = ntot / K[axis];
+  if (p->fp64)
+    hipLaunchKernelGGL(k_mixed_dft_q32<double>, dim3((unsigned)rows, (unsigned)ncomp), dim3(64),
+                       sizeof(cpx<double>) * K[axis], p->stream, (cpx<double>*)data, K[axis], stride[axis], ntot,
+                       (int)sign, p->q32_nodes[axis], p->q32_scale, (double*)nullptr,
+                       (unsigned long long*)nullptr);
+  else
+    hipLaunchKernelGGL(k_mixed_dft_q32<float>, dim3((unsigned)rows, (unsigned)ncomp), dim3(64),
+                       sizeof(cpx<float>) * K[axis], p->stream, (cpx<float>*)data, K[axis], stride[axis], ntot,
+                       (int)sign, p->q32_nodes[axis], p->q32_scale, (float*)nullptr, (unsigned long long*)nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(p, e, "int32 transform launch");
   return DPLR_LR_OK;
 }
 

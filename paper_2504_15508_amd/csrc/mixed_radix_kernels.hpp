@@ -322,7 +322,8 @@ __global__ void __launch_bounds__(256) k_mixed_fft_axis(cpx<T>* __restrict__ dat
 template <typename T>
 __global__ void __launch_bounds__(256) k_mixed_dft_q32(cpx<T>* __restrict__ data, int N, int64_t stride,
                                                        int64_t comp_stride, int sign, int nodes, double scale,
-                                                       T* __restrict__ packed) {
+                                                       T* __restrict__ packed,
+                                                       unsigned long long* __restrict__ clamped) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<T>* a = reinterpret_cast<cpx<T>*>(smem);
   const int64_t r = blockIdx.x;
@@ -331,21 +332,29 @@ __global__ void __launch_bounds__(256) k_mixed_dft_q32(cpx<T>* __restrict__ data
   for (int e = threadIdx.x; e < N; e += blockDim.x) a[e] = row[(int64_t)e * stride];
   __syncthreads();
   const int seg = N / nodes;
-  const T sc = (T)scale;
+  unsigned nclamp = 0;
   for (int k = threadIdx.x; k < N; k += blockDim.x) {
     long long acc_re = 0, acc_im = 0;
     for (int bk = 0; bk < nodes; ++bk) {
       cpx<T> s = {(T)0, (T)0};
       for (int n = bk * seg; n < (bk + 1) * seg; ++n)
         s = cadd(s, cmul(a[n], unit_root<T>((int)(((int64_t)n * k) % N), N, sign)));
-      // the product and its rounding in the plan's precision, the clamp in FP64
-      acc_re += (long long)fmin(fmax((double)rint(s.x * sc), -2147483648.0), 2147483647.0);
-      acc_im += (long long)fmin(fmax((double)rint(s.y * sc), -2147483648.0), 2147483647.0);
+      // the partial value (in the plan's precision) scaled, rounded to the
+      // nearest integer and clamped to int32 in FP64, so that the rounding is
+      // to the integer nearest the partial value in FP32 plans too
+      const double vr = rint((double)s.x * scale), vi = rint((double)s.y * scale);
+      const double cr = fmin(fmax(vr, -2147483648.0), 2147483647.0);
+      const double ci = fmin(fmax(vi, -2147483648.0), 2147483647.0);
+      nclamp += (cr != vr) + (ci != vi);
+      acc_re += (long long)cr;
+      acc_im += (long long)ci;
     }
     const cpx<T> v = {(T)((double)acc_re / scale), (T)((double)acc_im / scale)};
     if (packed) packed[4 * (rbase + (int64_t)k * stride) + blockIdx.y] = v.x;
     else row[(int64_t)k * stride] = v;
   }
+  // partial values that hit the int32 limits (saturated), counted for the caller
+  if (clamped && nclamp) atomicAdd(clamped, (unsigned long long)nclamp);
 }
 
 // Energy/virial summands and the ik field spectra over the full spectrum:

@@ -449,6 +449,33 @@ __device__ __forceinline__ int range_index(const Ranges& R, int v) {
   return R.lo[r] + (v - R.pre[r]);
 }
 
+// The same for at most two ranges (consecutive planes of one split are
+// contiguous in the sorted order, so a run of planes is one range, or two
+// where it wraps past the last plane); pre[1] is the total when n == 1.
+__device__ __forceinline__ int range_index2(const Ranges& R, int v) {
+  const int p1 = R.pre[1];
+  return v < p1 ? R.lo[0] + v : R.lo[1] + (v - p1);
+}
+
+// Blocks are dealt to the 8 XCDs of the device round-robin (block b runs on
+// XCD b mod 8).  Block b of a per-plane kernel with Kz planes and nsplit
+// particle splits serves (plane z, split): with Kz a multiple of 8, XCD x
+// takes the slab of planes [x Kz/8, (x+1) Kz/8) for every split, so its L2
+// holds the particles (and mesh rows) of one slab plus its stencil overhang
+// instead of every plane.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ void plane_of_block(int b, int Kz, int nsplit, int& z, int& split) {
+  if ((Kz % kNumXcd) == 0) {
+    const int xcd = b % kNumXcd, j = b / kNumXcd;
+    split = j % nsplit;
+    z = xcd * (Kz / kNumXcd) + j / nsplit;
+  } else {
+    z = b % Kz;
+    split = b / Kz;
+  }
+}
+
+
 // ----------------------------------------------------------------------------
 // 64-bit fixed-point charge accumulators.  FP32 plans scale every term by a
 // power of two S = 2^(30 - e), with 2^e > max |q| over the particles: a term
@@ -690,7 +717,8 @@ __global__ void __launch_bounds__(1024) k_spread_xy(const T4<T>* __restrict__ so
   __shared__ Ranges R;
   __shared__ unsigned qm_s;
 
-  const int z = blockIdx.x % Kz, split = blockIdx.x / Kz;
+  int z, split;
+  plane_of_block(blockIdx.x, Kz, g.nsplit, z, split);
   // global loads first (range bounds, charge maxima), so that their latencies
   // overlap each other and the clearing of the accumulators
   const RangeLoad rl = range_load(bin_start, g, split, z - (P - 1), min(P, Kz), 0, g.NQ);
@@ -723,7 +751,7 @@ __global__ void __launch_bounds__(1024) k_spread_xy(const T4<T>* __restrict__ so
     for (int u = 0; u < PB; ++u) {
       const int v = v0 + u * blockDim.x;
       if (v < total) {
-        const int idx = range_index(R, v);
+        const int idx = range_index2(R, v);  // the P planes below z: at most two ranges
         pts[u] = sorted[idx];
         sps[u] = sidx[idx];
       }

@@ -165,6 +165,29 @@ class Plan:
         return {lib.dplr_lr_profile_stage_name(i).decode(): (float(ms[i]), int(calls[i]))
                 for i in range(n.value)}
 
+    def q32_clamped(self) -> int:
+        """Partial values the int32 transforms of the last compute clamped
+        (synchronises)."""
+        c = self.debug_buffer(_lib.BUF_Q32_CLAMPED)
+        torch.cuda.synchronize(self.device)
+        return int(c.item())
+
+    def debug_dft_q32(self, axis: int, sign: int, data: torch.Tensor) -> torch.Tensor:
+        """One axis of the int32-quantised transform, in place on a complex
+        tensor [ncomp][Kz][Ky][Kx] (or [Kz][Ky][Kx]) of the plan's precision."""
+        cdt = torch.complex128 if self.precision == "fp64" else torch.complex64
+        if data.dtype != cdt or data.device != self.device or not data.is_contiguous():
+            raise ValueError(f"data must be a contiguous {cdt} tensor on {self.device}")
+        kx, ky, kz = self.mesh
+        ncomp = data.numel() // (kx * ky * kz)
+        if ncomp * kx * ky * kz != data.numel():
+            raise ValueError("data must hold whole [Kz][Ky][Kx] meshes")
+        with torch.cuda.device(self.device):
+            self._bind_stream()
+            self._check(_lib.load().dplr_lr_debug_dft_q32(self._h, int(axis), int(sign),
+                                                          ctypes.c_void_p(data.data_ptr()), int(ncomp)))
+        return data
+
     def debug_buffer(self, which: int) -> torch.Tensor:
         """Copy of an intermediate buffer of the last compute (see include/dplr_lr.h)."""
         lib = _lib.load()
@@ -178,6 +201,8 @@ class Plan:
             self._check(lib.dplr_lr_debug_copy(self._h, which, ctypes.c_void_p(out.data_ptr()), nbytes))
         kx, ky, kz = self.mesh
         kh = kx // 2 + 1
+        if which == _lib.BUF_Q32_CLAMPED:
+            return out.view(torch.int64)
         if which == _lib.BUF_INFLUENCE:
             return out.view(torch.float64).view(kh, ky // 2 + 1, kz // 2 + 1)
         cdt = torch.complex128 if self.precision == "fp64" else torch.complex64

@@ -101,3 +101,45 @@ def test_chain_through_synthetic_wannier_model(torch):
             errs.append(abs(fd - g[j, a]) / max(1.0, abs(g).max()))
     print(f"chain rule max err {max(errs):.2e}")
     assert max(errs) < 1e-6
+
+
+def test_chain_through_synthetic_wannier_model_vs_oracle(torch):
+    """The same chain against the oracle: the expected atom gradient is
+    -F_ion - J^T F_wc, with F_ion, F_wc the FP64 PPPM oracle's forces at the
+    atoms and at the WCs W(R), and J = dW/dR the Jacobian of the synthetic
+    Delta (its vector-Jacobian product taken by torch on the CPU; no GPU
+    value enters the expectation).  Same mesh and order on both sides, so the
+    bar is the FP64 parity bar."""
+    import paper_2504_15508_amd as dl
+    from oracle import pppm
+    s = systems.workload(1).system()
+    mesh, order = 32, 6
+    p = dl.Plan(mesh, order=order, beta=BETA, coulomb_k=KE, precision="fp64", capacity=s.n)
+    p.set_box(s.box)
+
+    def wannier(ion):
+        o, h1, h2 = ion[0::3], ion[1::3], ion[2::3]
+        bis = (h1 + h2) * 0.5 - o
+        return o + 0.25 * bis / bis.norm(dim=1, keepdim=True) * (1 + 0.1 * torch.tanh(o[:, :1] - 6.0))
+
+    qi = torch.tensor(s.ion_q, dtype=torch.float64, device="cuda")
+    qw = torch.tensor(s.wc_q, dtype=torch.float64, device="cuda")
+    ion = torch.tensor(s.ion_pos, dtype=torch.float64, device="cuda", requires_grad=True)
+    dl.dplr_long_range(ion, wannier(ion), qi, qw, p).backward()
+    g = ion.grad.cpu().numpy()
+
+    ion_c = torch.tensor(s.ion_pos, dtype=torch.float64, requires_grad=True)   # CPU
+    w_c = wannier(ion_c)
+    pos = np.concatenate([s.ion_pos, w_c.detach().numpy()])
+    q = np.concatenate([s.ion_q, s.wc_q])
+    _, F0, _ = pppm.pppm(pos, q, s.box, (mesh,) * 3, order, BETA, KE)
+    F_ion, F_wc = F0[: s.n_ion], F0[s.n_ion:]
+    (jt,) = torch.autograd.grad(w_c, ion_c, grad_outputs=torch.tensor(-F_wc, dtype=torch.float64))
+    expect = -F_ion + jt.numpy()
+    err = float(np.linalg.norm(g - expect) / np.linalg.norm(expect))
+    err_max = float(np.abs(g - expect).max() / np.abs(expect).max())
+    # the WC term must matter: dropping it changes the gradient at O(1)
+    drop = float(np.linalg.norm(-F_ion - expect) / np.linalg.norm(expect))
+    print(f"chain rule vs oracle: rel {err:.2e}, max {err_max:.2e} (without the WC term: {drop:.2e})")
+    assert err <= 1e-9 and err_max <= 1e-9
+    assert drop > 1e-2

@@ -78,7 +78,7 @@ def test_forward_matches_oracle(torch, small):
     e = np.linalg.norm(dF - ref) / np.linalg.norm(ref)
     e64 = np.linalg.norm(dF - ref64) / np.linalg.norm(ref64)
     print(f"forward rel err vs bf16-emulating oracle {e:.2e}, vs FP64 oracle {e64:.2e}")
-    assert e < 5e-3
+    assert e < 2e-3      # measured on MI355X: 3.2e-4 (bf16 rounding decisions that flip)
     assert e64 < 5e-2
 
 
@@ -93,13 +93,18 @@ def test_gradients_and_adam_match_oracle(torch, small):
             _t(torch, target[: s.n_ion]), _t(torch, target[s.n_ion:])]
     loss, g = m.train_step(s.box, *args, lr=0.0, want_grad=True)
     dF, cache = OL.forward(p, T0, D0, s.all_q(), mu, isd, 0.01, emulate_bf16=True)
-    loss0, g0 = OL.loss_and_grad(p, cache, dF, target)
+    # the oracle rounds the backward's layer-output gradients to bf16 where the
+    # kernel does; what remains is FP32 accumulation order and the rare bf16
+    # rounding decision that the two sides take differently
+    loss0, g0 = OL.loss_and_grad(p, cache, dF, target, emulate_bf16=True)
+    _, g64 = OL.loss_and_grad(p, cache, dF, target)
     assert abs(float(loss) - loss0) <= 1e-3 * loss0
     gd = L.unpack(np.concatenate([g.cpu().numpy(), np.zeros(256, np.float32)]))
     for k in ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"):
         e = np.linalg.norm(gd[k] - g0[k]) / np.linalg.norm(g0[k])
-        print(f"grad {k}: rel err {e:.2e}")
-        assert e < 3e-2, k
+        e64 = np.linalg.norm(gd[k] - g64[k]) / np.linalg.norm(g64[k])
+        print(f"grad {k}: rel err {e:.2e} vs the bf16-emulating oracle, {e64:.2e} vs unrounded dz")
+        assert e < 1e-3, k   # measured on MI355X: at most 1.6e-4
     # one Adam step with the GPU's own gradient reproduces the oracle update
     before = m.get_params()
     loss, g = m.train_step(s.box, *args, lr=1e-3, want_grad=True)

@@ -48,6 +48,14 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+def rel_max(a, b):
+    """Largest error of any force component over the largest reference
+    component: the per-element bound beside the relative RMSE (a few bad
+    elements cannot hide in the norm)."""
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
 def check_vs_pppm(torch, sys, mesh, order, precision, tol_f, tol_e, tol_w, alias=2):
     E, fi, fw, W, _ = run_gpu(torch, sys, mesh, order, precision, alias)
     ref = sys.rounded(np.float32) if precision == "fp32" else sys
@@ -55,9 +63,10 @@ def check_vs_pppm(torch, sys, mesh, order, precision, tol_f, tol_e, tol_w, alias
     E0, F0, W0 = pppm.pppm(ref.all_pos(), ref.all_q(), ref.box, K, order, BETA, KE, alias)
     F = np.concatenate([fi, fw])
     print(f"{sys.name} K={K} p={order} {precision}: dE={abs(E - E0) / abs(E0):.2e} "
-          f"dF={rel(F, F0):.2e} dW={np.abs(W - W0).max() / abs(E0):.2e}", flush=True)
+          f"dF={rel(F, F0):.2e} dFmax={rel_max(F, F0):.2e} dW={np.abs(W - W0).max() / abs(E0):.2e}", flush=True)
     assert abs(E - E0) <= tol_e * abs(E0)
     assert rel(F, F0) <= tol_f
+    assert rel_max(F, F0) <= tol_f
     assert np.abs(W - W0).max() <= tol_w * abs(E0)
     return E, F, W
 
@@ -267,8 +276,10 @@ def test_ionic_256_matches_pppm_oracle_samples(torch_dev, ionic, precision, tol_
     F = np.concatenate([fi, fw])[idx]
     F0, E0, W0 = np.array(gold["sample_force"]), gold["energy"], np.array(gold["virial"])
     dF, dE, dW = rel(F, F0), abs(E - E0) / abs(E0), np.abs(W - W0).max() / abs(E0)
-    print(f"ionic 256^3 {precision} vs PPPM oracle: dF={dF:.2e} dE={dE:.2e} dW={dW:.2e}", flush=True)
+    print(f"ionic 256^3 {precision} vs PPPM oracle: dF={dF:.2e} dFmax={rel_max(F, F0):.2e} dE={dE:.2e} "
+          f"dW={dW:.2e}", flush=True)
     assert dF <= tol_f
+    assert rel_max(F, F0) <= tol_f
     assert dE <= tol_e
     assert dW <= tol_e
 

@@ -124,3 +124,25 @@ def test_bf16_rounding_edges():
     v = L.bf16(np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -9, -3.0, 1e-40, np.inf]))
     assert v[0] == 1.0 and v[1] == 1.0 and v[2] == 1 + 2 ** -7 and v[3] == -3.0 and v[5] == np.inf
     assert abs(v[4]) < 1e-38
+
+
+def test_bf16_emulated_backward_is_a_small_rounding_of_the_exact_one():
+    # the emulation only rounds the layer-output gradients: every parameter
+    # gradient moves by bf16-level amounts (not zero, not O(1)), and with the
+    # flag off the function is the exact chain rule pinned above
+    rng = np.random.default_rng(4)
+    n = 40
+    T = rng.normal(0, 1, (n, L.NK, L.NL))
+    D = np.einsum("nka,nla->nkl", T, T[:, :L.NL, :]).reshape(n, -1)
+    q = rng.choice([6.0, 1.0, -8.0], n)
+    p = L.init_params(2)
+    for k in ("b1", "b2", "b3", "b4"):
+        p[k] = rng.normal(0, 0.1, p[k].shape)
+    mu, isd = D.mean(0), 1.0 / (D.std(0) + 1e-3)
+    dF, cache = L.forward(p, T, D, q, mu, isd, 0.01, emulate_bf16=True)
+    target = rng.normal(0, 0.05, dF.shape)
+    _, g_exact = L.loss_and_grad(p, cache, dF, target)
+    _, g_emul = L.loss_and_grad(p, cache, dF, target, emulate_bf16=True)
+    for k in g_exact:
+        d = np.linalg.norm(g_emul[k] - g_exact[k]) / np.linalg.norm(g_exact[k])
+        assert 1e-6 < d < 2e-2, (k, d)
