@@ -68,3 +68,27 @@ def recip_general(pos, q, hmat, beta: float, ke: float, mcut: float):
     f = np.exp(-math.pi ** 2 * m2 / beta ** 2) / m2
     S = q @ np.exp(2j * math.pi * (pos @ m.T))
     return ke / (2 * math.pi * V) * float((f * (S.conj() * S).real).sum())
+
+
+def recip_forces_mesh_modes(pos, q, box, beta: float, ke: float, K):
+    """Reciprocal forces of the E_Gt sum restricted to the wave vectors a mesh
+    of K[a] points per axis holds: m = n / L with 0 < |n_a| <= K[a] / 2 on every
+    axis (the cube of mesh modes, not a sphere).  With K large enough to hold
+    every mode of weight above rounding it is the full sum; for a coarse mesh
+    it is the best any method limited to that mesh's modes can do, with no
+    aliasing or assignment error."""
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    V = float(np.prod(box))
+    g = [np.arange(-(int(K[a]) // 2), int(K[a]) // 2 + 1) for a in range(3)]
+    n = np.stack(np.meshgrid(*g, indexing="ij"), axis=-1).reshape(-1, 3)
+    m = n / box
+    m2 = (m * m).sum(1)
+    keep = m2 > 0
+    m, m2 = m[keep], m2[keep]
+    f = np.exp(-math.pi ** 2 * m2 / beta ** 2) / m2
+    ph = np.exp(2j * math.pi * (pos @ m.T))
+    S = q @ ph
+    im = (S.conj()[None, :] * ph).imag
+    return (2 * ke / V) * q[:, None] * ((im * f[None, :]) @ m)

@@ -168,3 +168,23 @@ def test_invalid_arguments_rejected(ewald):
         ewald.recip(np.zeros((2, 3)), np.zeros(2), [0.0, 1.0, 1.0], BETA, KE)
     with pytest.raises(ValueError):
         ewald.recip(np.zeros((2, 3)), np.zeros(2), [1.0, 1.0, 1.0], BETA, KE, force_idx=[5])
+
+
+def test_mesh_mode_restricted_forces(ewald):
+    """recip_forces_mesh_modes: with a cube of modes that holds the whole
+    converged sphere it is the full reciprocal sum (the C oracle); restricted
+    to the modes of a 2.02 A mesh on the spacing-matched training box it misses
+    Ewald by more than 1e-2 (the floor quoted for the learned coarse form)."""
+    from oracle import ewald_np
+    s = systems.workload(1).system()
+    pos, q = s.all_pos(), s.all_q()
+    _, _, F0 = ewald.recip(pos, q, s.box, systems.BETA, systems.COULOMB_K)
+    nmax = int(np.ceil(ewald.mcut_for(systems.BETA) * s.box[0]))
+    F1 = ewald_np.recip_forces_mesh_modes(pos, q, s.box, systems.BETA, systems.COULOMB_K, (2 * nmax + 2,) * 3)
+    assert np.linalg.norm(F1 - F0) <= 1e-12 * np.linalg.norm(F0)
+    t = systems.training_box(0)
+    pos, q = t.all_pos(), t.all_q()
+    _, _, Fe = ewald.recip(pos, q, t.box, systems.BETA, systems.COULOMB_K)
+    Ft = ewald_np.recip_forces_mesh_modes(pos, q, t.box, systems.BETA, systems.COULOMB_K, (16, 16, 16))
+    floor = np.linalg.norm(Ft - Fe) / np.linalg.norm(Fe)
+    assert 1e-2 < floor < 2e-2
