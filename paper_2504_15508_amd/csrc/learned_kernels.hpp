@@ -29,7 +29,8 @@ constexpr int kNParams = kOffIsd + kIn;               // packed total
 constexpr int kNWeights = kIn * kH + 2 * kH * kH + kH * kOut;  // bf16 weight copy
 constexpr int kRows = 128;                            // particles per MLP block (4 waves x 32)
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
@@ -245,7 +246,7 @@ __global__ void __launch_bounds__(kDescThreads) k_descriptor(const float4* __res
 // ---------------------------------------------------------------------------
 // LDS operand layout for the MFMA tiles: every matrix is stored with the
 // contraction index k contiguous and rows padded by 4 bf16 (8 bytes), so a
-// lane's four k values are one 64-bit LDS read and the 32 rows a half-wave
+// lane's eight k values are two 64-bit LDS reads and the 32 rows a half-wave
 // reads fall on distinct banks (row pitch / 8 bytes is odd).
 // ---------------------------------------------------------------------------
 constexpr int kPadIn = kIn + 4;     // 132: rows of 128 bf16
@@ -254,19 +255,25 @@ constexpr int kPadO = kOut + 4;     // 36: rows of 32 bf16
 constexpr int kPadRows = kRows + 4; // 132: transposed tiles (rows = features, k = particles)
 
 // acc (32 x 32) += A (32 x K) * B (K x 32) with both operands k-contiguous:
-// A(m, k) = A[m * lda + k], B(k, n) = B[n * ldb + k]; lane l supplies
-// A(l % 32, 4 (l / 32) + i) and B(4 (l / 32) + i, l % 32), i < 4.
+// A(m, k) = A[m * lda + k], B(k, n) = B[n * ldb + k].  One gfx950
+// v_mfma_f32_32x32x16_bf16 per 16 values of k: lane l supplies
+// A(l % 32, 8 (l / 32) + i) and B(8 (l / 32) + i, l % 32), i < 8, read as two
+// 8-byte LDS loads (rows are 8-byte aligned); K is a multiple of 16.
 __device__ __forceinline__ void mfma_tile_kc(f32x16& acc, const unsigned short* A, int lda,
                                              const unsigned short* B, int ldb, int K) {
   const int l = threadIdx.x & 63;
-  const int mn = l & 31, kh = (l >> 5) * 4;
+  const int mn = l & 31, kh = (l >> 5) * 8;
   const unsigned short* pa = A + mn * lda + kh;
   const unsigned short* pb = B + mn * ldb + kh;
 #pragma unroll 4
-  for (int k0 = 0; k0 < K; k0 += 8) {
-    const bf16x4 a = *reinterpret_cast<const bf16x4*>(pa + k0);
-    const bf16x4 b = *reinterpret_cast<const bf16x4*>(pb + k0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bf16x4 a0 = *reinterpret_cast<const bf16x4*>(pa + k0);
+    const bf16x4 a1 = *reinterpret_cast<const bf16x4*>(pa + k0 + 4);
+    const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(pb + k0);
+    const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(pb + k0 + 4);
+    const bf16x8 a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+    const bf16x8 b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
   }
 }
 
