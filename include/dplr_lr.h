@@ -293,19 +293,36 @@ dplr_lr_status dplr_lr_mlp_set_params(dplr_lr_mlp m, const float* host_params, i
 dplr_lr_status dplr_lr_mlp_get_params(dplr_lr_mlp m, float* host_params, int64_t count);
 /* dF for every particle, written (accumulate = 0) or added (accumulate != 0)
  * to ion_dF / wc_dF.  The first call for a larger box grows the cell list
- * (device allocation); later calls allocate nothing. */
+ * (device allocation); later calls allocate nothing.  Neighbours are taken in
+ * a fixed order (cells in order, particles of a cell in original-index
+ * order), so repeated calls give bitwise equal results.  Each call also
+ * records, for dplr_lr_mlp_read_stats, the largest |dF_i|, the largest |F_i|
+ * of the arrays it adds to (accumulate != 0; the forces being corrected) and
+ * the smallest and largest neighbour count within the cutoff. */
 dplr_lr_status dplr_lr_mlp_forward(dplr_lr_mlp m, const double box[3], int64_t n_ion, const float* ion_pos,
                                    const float* ion_q, int64_t n_wc, const float* wc_pos, const float* wc_q,
                                    float* ion_dF, float* wc_dF, int32_t accumulate);
 /* One training step on the mean-squared error between dF and the targets:
  * forward, backward (BF16 MFMA, FP32 accumulate), deterministic gradient sum
- * and, when lr > 0, an Adam update (beta 0.9 / 0.999, eps 1e-8).  *loss
- * (device double) receives the loss before the update; grad_out (device
- * float[count of trainable parameters], may be NULL) the gradient. */
+ * and, when lr > 0, an Adam update (beta 0.9 / 0.999, eps 1e-8).  The target
+ * of particle i is target_i - base_i when the base arrays are given (pass
+ * the fine-mesh forces as target and the coarse-mesh forces as base to train
+ * on the residual), else target_i; both base pointers NULL or both set.
+ * *loss (device double) receives the loss before the update; grad_out
+ * (device float[count of trainable parameters], may be NULL) the gradient. */
 dplr_lr_status dplr_lr_mlp_train_step(dplr_lr_mlp m, const double box[3], int64_t n_ion, const float* ion_pos,
                                       const float* ion_q, int64_t n_wc, const float* wc_pos, const float* wc_q,
-                                      const float* ion_target, const float* wc_target, float lr, double* loss,
-                                      float* grad_out);
+                                      const float* ion_target, const float* wc_target, const float* ion_base,
+                                      const float* wc_base, float lr, double* loss, float* grad_out);
+/* Input normalisation from training configurations: norm_accumulate adds
+ * the invariants D_i of one configuration to FP64 sums (sum D, sum D^2, max
+ * |D|, count; fixed-order reductions); norm_finish sets mu = mean and
+ * inv_sigma = 1 / (std + 1e-6 (max |D| + 1)) in the parameters (device) and
+ * clears the sums.  Stream-ordered, no host synchronisation. */
+dplr_lr_status dplr_lr_mlp_norm_accumulate(dplr_lr_mlp m, const double box[3], int64_t n_ion, const float* ion_pos,
+                                           const float* ion_q, int64_t n_wc, const float* wc_pos,
+                                           const float* wc_q);
+dplr_lr_status dplr_lr_mlp_norm_finish(dplr_lr_mlp m);
 /* The descriptor T (device float [n][128], index 4k + a) in the network's
  * cell order, and that order (device int [n], original particle indices;
  * ions first).  Either output may be NULL. */
@@ -314,10 +331,29 @@ dplr_lr_status dplr_lr_mlp_descriptor(dplr_lr_mlp m, const double box[3], int64_
                                       float* T_sorted, int32_t* order);
 const char* dplr_lr_mlp_last_error(dplr_lr_mlp m);
 
-/* Fallback guard (host only).  The learned form is used only while the
- * inputs look like the training data and periodic audits (a fine-mesh
- * recomputation compared with the learned result) stay within tolerance;
- * otherwise the caller runs the fine plan. */
+/* Fallback guard.  The learned form is used only while the inputs look
+ * like the training data and periodic audits (a fine-mesh recomputation
+ * compared with the learned result) stay within tolerance; otherwise the
+ * caller runs the fine plan.  The statistics come from the device:
+ *   set_train_charges  the charges present in training (host, at most 16);
+ *   check_charges      counts particles whose charge is not one of them;
+ *   audit              sum |F - F_ref|^2 and sum |F_ref|^2 over both sets
+ *                      (FP64, fixed order), replacing (accumulate = 0) or
+ *                      adding to (accumulate != 0) the previous audit sums;
+ *   read_stats         synchronises the network's stream and fills
+ *                      max_correction, max_force and the neighbour range of
+ *                      the last forward (min_neighbours = HUGE_VAL and
+ *                      max_neighbours = 0 when it saw no particle, a range
+ *                      no bound rejects), unseen_charges of the last check,
+ *                      and audit_valid / audit_rel_rmse = sqrt(sum / sum) of
+ *                      the audit sums; steps_since_audit is left to the
+ *                      caller.
+ * dplr_lr_guard_decide is host-only. */
+dplr_lr_status dplr_lr_mlp_set_train_charges(dplr_lr_mlp m, const float* host_charges, int32_t count);
+dplr_lr_status dplr_lr_mlp_check_charges(dplr_lr_mlp m, int64_t n_ion, const float* ion_q, int64_t n_wc,
+                                         const float* wc_q);
+dplr_lr_status dplr_lr_mlp_audit(dplr_lr_mlp m, int64_t n_ion, const float* ion_force, const float* ion_ref,
+                                 int64_t n_wc, const float* wc_force, const float* wc_ref, int32_t accumulate);
 #define DPLR_LR_GUARD_LEARNED 0
 #define DPLR_LR_GUARD_FINE 1
 #define DPLR_LR_GUARD_AUDIT 2
@@ -335,6 +371,7 @@ typedef struct {
   double min_neighbours, max_neighbours;
   int32_t unseen_charges;       /* particles whose charge was absent from training   */
 } dplr_lr_guard_stats;
+dplr_lr_status dplr_lr_mlp_read_stats(dplr_lr_mlp m, dplr_lr_guard_stats* out);
 /* *decision = DPLR_LR_GUARD_LEARNED, _FINE or _AUDIT (run both and compare). */
 dplr_lr_status dplr_lr_guard_decide(const dplr_lr_guard_config* cfg, const dplr_lr_guard_stats* stats,
                                     int32_t* decision);

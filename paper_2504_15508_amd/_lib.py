@@ -30,6 +30,8 @@ EXPORTS = [
     "dplr_lr_mlp_config_default", "dplr_lr_mlp_param_count", "dplr_lr_mlp_create", "dplr_lr_mlp_destroy",
     "dplr_lr_mlp_set_stream", "dplr_lr_mlp_set_params", "dplr_lr_mlp_get_params", "dplr_lr_mlp_forward",
     "dplr_lr_mlp_train_step", "dplr_lr_mlp_descriptor", "dplr_lr_mlp_last_error", "dplr_lr_guard_decide",
+    "dplr_lr_mlp_norm_accumulate", "dplr_lr_mlp_norm_finish", "dplr_lr_mlp_set_train_charges",
+    "dplr_lr_mlp_check_charges", "dplr_lr_mlp_audit", "dplr_lr_mlp_read_stats",
 ]
 GUARD_LEARNED, GUARD_FINE, GUARD_AUDIT = 0, 1, 2
 
@@ -105,8 +107,14 @@ def load():
         "dplr_lr_mlp_set_params": ([p, p, i64], ctypes.c_int),
         "dplr_lr_mlp_get_params": ([p, p, i64], ctypes.c_int),
         "dplr_lr_mlp_forward": ([p, ctypes.POINTER(d), i64, p, p, i64, p, p, p, p, i32], ctypes.c_int),
-        "dplr_lr_mlp_train_step": ([p, ctypes.POINTER(d), i64, p, p, i64, p, p, p, p, ctypes.c_float, p, p],
+        "dplr_lr_mlp_train_step": ([p, ctypes.POINTER(d), i64, p, p, i64, p, p, p, p, p, p, ctypes.c_float, p, p],
                                    ctypes.c_int),
+        "dplr_lr_mlp_norm_accumulate": ([p, ctypes.POINTER(d), i64, p, p, i64, p, p], ctypes.c_int),
+        "dplr_lr_mlp_norm_finish": ([p], ctypes.c_int),
+        "dplr_lr_mlp_set_train_charges": ([p, p, i32], ctypes.c_int),
+        "dplr_lr_mlp_check_charges": ([p, i64, p, i64, p], ctypes.c_int),
+        "dplr_lr_mlp_audit": ([p, i64, p, p, i64, p, p, i32], ctypes.c_int),
+        "dplr_lr_mlp_read_stats": ([p, ctypes.POINTER(GuardStats)], ctypes.c_int),
         "dplr_lr_mlp_descriptor": ([p, ctypes.POINTER(d), i64, p, p, i64, p, p, p, p], ctypes.c_int),
         "dplr_lr_mlp_last_error": ([p], ctypes.c_char_p),
         "dplr_lr_guard_decide": ([ctypes.POINTER(GuardConfig), ctypes.POINTER(GuardStats), ctypes.POINTER(i32)],

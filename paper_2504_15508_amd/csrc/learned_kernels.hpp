@@ -106,6 +106,237 @@ __global__ void k_cell_scatter(const float* __restrict__ ion_pos, const float* _
   cidx[slot] = (int)i;
 }
 
+// The atomic scatter leaves each cell's particles in arrival order; this puts
+// them in order of original index (rank = number of the cell's particles
+// with a smaller index), so the cell order and every sum over neighbours
+// taken in it are the same on every call.  One thread per particle; a cell
+// holds tens of particles, so the O(n^2) ranking per cell is cheap.
+__global__ void k_cell_order(const float4* __restrict__ cpos_in, const int* __restrict__ cidx_in,
+                             const int* __restrict__ start, int n,
+                             float4* __restrict__ cpos, int* __restrict__ cidx, CellGeo c) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const float4 p = cpos_in[e];
+  const int id = cidx_in[e];
+  const int cell = cell_of(p.x, p.y, p.z, c);
+  const int j0 = start[cell], j1 = start[cell + 1];
+  int rank = 0;
+  for (int j = j0; j < j1; ++j) rank += cidx_in[j] < id;
+  cpos[j0 + rank] = p;
+  cidx[j0 + rank] = id;
+}
+
+// Runtime statistics of the learned form's inputs and outputs, read by the
+// fallback guard (dplr_lr_mlp_read_stats).  Maxima of non-negative floats are
+// kept as their bit patterns (whose unsigned order is the float order), so
+// every field is an integer reduction or a fixed-order FP64 sum: the values do
+// not depend on the order of the contributions.
+struct Stats {
+  unsigned max_corr_bits;   // max |dF_i| of the last forward
+  unsigned max_force_bits;  // max |F_i| of the forces the last forward added to
+  int min_nbr, max_nbr;     // neighbour counts within the cutoff, last forward
+  int unseen;               // charges outside the training set, last check
+  int audit_valid;
+  double audit_num, audit_den;  // sum |F - F_ref|^2, sum |F_ref|^2 of the audits
+};
+
+__device__ __forceinline__ unsigned wave_max_bits(unsigned v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, off, 64));
+  return v;
+}
+
+__global__ void k_stats_reset_forward(Stats* st) {
+  if (threadIdx.x == 0) {
+    st->max_corr_bits = 0u;
+    st->max_force_bits = 0u;
+    st->min_nbr = 0x7fffffff;
+    st->max_nbr = 0;
+  }
+}
+
+// Smallest and largest neighbour count: per-block partials, then one block
+// reduces them (integer min / max: independent of the order).
+__global__ void __launch_bounds__(256) k_nbr_partials(const int* __restrict__ nbr, int n, int* __restrict__ part) {
+  __shared__ int lo[256], hi[256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  lo[threadIdx.x] = i < n ? nbr[i] : 0x7fffffff;
+  hi[threadIdx.x] = i < n ? nbr[i] : 0;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      lo[threadIdx.x] = min(lo[threadIdx.x], lo[threadIdx.x + h]);
+      hi[threadIdx.x] = max(hi[threadIdx.x], hi[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = lo[0];
+    part[2 * blockIdx.x + 1] = hi[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_nbr_range(const int* __restrict__ part, int nblk, Stats* __restrict__ st) {
+  __shared__ int lo[256], hi[256];
+  int a = 0x7fffffff, b = 0;
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+    a = min(a, part[2 * k]);
+    b = max(b, part[2 * k + 1]);
+  }
+  lo[threadIdx.x] = a;
+  hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      lo[threadIdx.x] = min(lo[threadIdx.x], lo[threadIdx.x + h]);
+      hi[threadIdx.x] = max(hi[threadIdx.x], hi[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->min_nbr = lo[0];
+    st->max_nbr = hi[0];
+  }
+}
+
+// Charges not in the training set (exact float comparison with the set).
+constexpr int kMaxTrainCharges = 16;
+struct ChargeSet {
+  int n;
+  float q[kMaxTrainCharges];
+};
+
+__global__ void k_check_charges(const float* __restrict__ ion_q, const float* __restrict__ wc_q, int64_t n_ion,
+                                int64_t n, ChargeSet cs, Stats* st, int reset) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (reset) {  // single-block launch for an empty input
+    if (i == 0) st->unseen = 0;
+    return;
+  }
+  int bad = 0;
+  if (i < n) {
+    const float q = (i < n_ion) ? ion_q[i] : wc_q[i - n_ion];
+    bool seen = false;
+    for (int k = 0; k < cs.n; ++k) seen |= (q == cs.q[k]);
+    bad = seen ? 0 : 1;
+  }
+  for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(&st->unseen, bad);
+}
+
+// Audit sums over both particle sets: per-block FP64 partials (fixed order
+// inside the block), then one block adds them in block order.
+__global__ void __launch_bounds__(256) k_audit_partials(const float* __restrict__ fi, const float* __restrict__ ri,
+                                                        int64_t n_ion, const float* __restrict__ fw,
+                                                        const float* __restrict__ rw, int64_t n,
+                                                        double* __restrict__ part) {
+  __shared__ double red[2][256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double num = 0.0, den = 0.0;
+  if (i < n) {
+    const float* f = (i < n_ion) ? fi + 3 * i : fw + 3 * (i - n_ion);
+    const float* r = (i < n_ion) ? ri + 3 * i : rw + 3 * (i - n_ion);
+    for (int a = 0; a < 3; ++a) {
+      const double d = (double)f[a] - (double)r[a];
+      num += d * d;
+      den += (double)r[a] * (double)r[a];
+    }
+  }
+  red[0][threadIdx.x] = num;
+  red[1][threadIdx.x] = den;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + h];
+      red[1][threadIdx.x] += red[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0][0];
+    part[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+__global__ void k_audit_finish(const double* __restrict__ part, int nblk, Stats* st, int accumulate) {
+  if (threadIdx.x != 0) return;
+  double num = 0.0, den = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    num += part[2 * b];
+    den += part[2 * b + 1];
+  }
+  st->audit_num = accumulate ? st->audit_num + num : num;
+  st->audit_den = accumulate ? st->audit_den + den : den;
+  st->audit_valid = 1;
+}
+
+// Input normalisation from training descriptors: per-block partial sums of
+// D_f and D_f^2 and the block maximum of |D| (f < 128), from T [n][128];
+// then the block partials are added in block order into acc[2][128] (+ count
+// and max), and finish turns them into mu = mean, inv_sigma =
+// 1 / (std + 1e-6 (max |D| + 1)) in the parameter vector.
+__global__ void __launch_bounds__(128) k_norm_partials(const float* __restrict__ T, int n, int rows_per_block,
+                                                       double* __restrict__ part) {
+  const int f = threadIdx.x;  // feature 4k + l
+  const int k = f >> 2, l = f & 3;
+  const int r0 = blockIdx.x * rows_per_block, r1 = min(n, r0 + rows_per_block);
+  double s1 = 0.0, s2 = 0.0;
+  float mx = 0.0f;
+  for (int r = r0; r < r1; ++r) {
+    const float4 tk = reinterpret_cast<const float4*>(T + (size_t)r * 128)[k];
+    const float4 tl = reinterpret_cast<const float4*>(T + (size_t)r * 128)[l];
+    const float d = tk.x * tl.x + tk.y * tl.y + tk.z * tl.z + tk.w * tl.w;
+    s1 += d;
+    s2 += (double)d * d;
+    mx = fmaxf(mx, fabsf(d));
+  }
+  double* p = part + (size_t)blockIdx.x * 3 * 128;
+  p[f] = s1;
+  p[128 + f] = s2;
+  p[256 + f] = mx;
+}
+
+__global__ void __launch_bounds__(128) k_norm_reduce(const double* __restrict__ part, int nblk, int rows,
+                                                     double* __restrict__ acc) {
+  // acc: [0,128) sum, [128,256) sum of squares, [256] max |D|, [257] count
+  const int f = threadIdx.x;
+  double s1 = 0.0, s2 = 0.0, mx = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    const double* p = part + (size_t)b * 3 * 128;
+    s1 += p[f];
+    s2 += p[128 + f];
+    mx = fmax(mx, p[256 + f]);
+  }
+  acc[f] += s1;
+  acc[128 + f] += s2;
+  __shared__ double m[128];
+  m[f] = mx;
+  __syncthreads();
+  if (f == 0) {
+    double g = acc[256];
+    for (int i = 0; i < 128; ++i) g = fmax(g, m[i]);
+    acc[256] = g;
+    acc[257] += (double)rows;
+  }
+}
+
+__global__ void __launch_bounds__(128) k_norm_finish(double* __restrict__ acc, float* __restrict__ params) {
+  const int f = threadIdx.x;
+  const double cnt = acc[257];
+  if (cnt > 0.0) {
+    const double mu = acc[f] / cnt;
+    const double var = fmax(acc[128 + f] / cnt - mu * mu, 0.0);
+    params[kOffMu + f] = (float)mu;
+    params[kOffIsd + f] = (float)(1.0 / (sqrt(var) + 1e-6 * (acc[256] + 1.0)));
+  }
+  __syncthreads();
+  acc[f] = 0.0;
+  acc[128 + f] = 0.0;
+  if (f == 0) {
+    acc[256] = 0.0;
+    acc[257] = 0.0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Descriptor: four lanes per (cell-sorted) particle.  Lane g owns the radial
 // orders k = g, g+4, ..., g+28, advanced with the stride-4 Chebyshev
@@ -163,7 +394,8 @@ __global__ void __launch_bounds__(kDescThreads) k_descriptor(const float4* __res
                                                              const int* __restrict__ start, int n,
                                                              const float* __restrict__ params,
                                                              float* __restrict__ Tout,
-                                                             unsigned short* __restrict__ X, CellGeo c) {
+                                                             unsigned short* __restrict__ X, CellGeo c,
+                                                             int* __restrict__ nbr) {
   __shared__ int lists[kDescParts][kNbrMax];
   const int g = threadIdx.x & (kDescLanes - 1), p = threadIdx.x / kDescLanes;
   const int lane = threadIdx.x & 63, gbase = lane & ~(kDescLanes - 1);
@@ -181,7 +413,7 @@ __global__ void __launch_bounds__(kDescThreads) k_descriptor(const float4* __res
   const int cy = min((int)(pi.y * c.cinv[1]), c.nc[1] - 1);
   const int cz = min((int)(pi.z * c.cinv[2]), c.nc[2] - 1);
   const float rc2 = c.rc * c.rc;
-  int cnt = 0;
+  int cnt = 0, total = 0;
   for (int dz = -1; dz <= 1; ++dz) {
     const int zz = (cz + dz + c.nc[2]) % c.nc[2];
     for (int dy = -1; dy <= 1; ++dy) {
@@ -205,6 +437,7 @@ __global__ void __launch_bounds__(kDescThreads) k_descriptor(const float4* __res
           const unsigned gm = (unsigned)(__ballot(in) >> gbase) & ((1u << kDescLanes) - 1u);
           if (in) list[cnt + __popc(gm & ((1u << g) - 1u))] = j;
           cnt += __popc(gm);
+          total += __popc(gm);
           if (cnt > kNbrMax - kDescLanes) {  // the same decision on all four lanes
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             accumulate_pairs(T, pi, cpos, list, cnt, g, c);
@@ -217,6 +450,7 @@ __global__ void __launch_bounds__(kDescThreads) k_descriptor(const float4* __res
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   accumulate_pairs(T, pi, cpos, list, cnt, g, c);
+  if (nbr && g == 0) nbr[i] = total;  // neighbour count, reduced by k_nbr_range
   float* to = Tout + (size_t)i * 128;
 #pragma unroll
   for (int m = 0; m < 8; ++m)
@@ -308,8 +542,10 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restric
                                                  int accumulate,
                                                  // training
                                                  const float* __restrict__ ion_tgt, const float* __restrict__ wc_tgt,
+                                                 const float* __restrict__ ion_base, const float* __restrict__ wc_base,
                                                  float* __restrict__ Z, unsigned short* __restrict__ H,
-                                                 float* __restrict__ dC, double* __restrict__ loss_part, float gscale) {
+                                                 float* __restrict__ dC, double* __restrict__ loss_part, float gscale,
+                                                 Stats* __restrict__ st) {
   extern __shared__ __align__(16) unsigned char smem[];
   FwdLds& S = *reinterpret_cast<FwdLds*>(smem);
   const int tid = threadIdx.x, wave = tid >> 6;
@@ -336,6 +572,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restric
   const unsigned short* wl[4] = {S.wt + kLW1t, S.wt + kLW2t, S.wt + kLW3t, S.wt + kLW4t};
   const int ldw[4] = {kPadIn, kPadH, kPadH, kPadH};
   double lsum = 0.0;
+  unsigned mcorr = 0u, mforce = 0u;  // running maxima (float bits) for the guard
   const int ntiles = (n + kRows - 1) / kRows;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int row0 = tile * kRows;
@@ -402,11 +639,21 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restric
       f0 *= sq; f1 *= sq; f2 *= sq;
       const int src = cidx[slot];
       float* out = (src < n_ion) ? ion_dF + 3 * (int64_t)src : wc_dF + 3 * ((int64_t)src - n_ion);
-      if (accumulate) { out[0] += f0; out[1] += f1; out[2] += f2; }
-      else { out[0] = f0; out[1] = f1; out[2] = f2; }
+      mcorr = max(mcorr, __float_as_uint(sqrtf(f0 * f0 + f1 * f1 + f2 * f2)));
+      if (accumulate) {
+        mforce = max(mforce, __float_as_uint(sqrtf(out[0] * out[0] + out[1] * out[1] + out[2] * out[2])));
+        out[0] += f0; out[1] += f1; out[2] += f2;
+      } else {
+        out[0] = f0; out[1] = f1; out[2] = f2;
+      }
       if (TRAIN) {
-        const float* tg = (src < n_ion) ? ion_tgt + 3 * (int64_t)src : wc_tgt + 3 * ((int64_t)src - n_ion);
-        const float e0 = f0 - tg[0], e1 = f1 - tg[1], e2 = f2 - tg[2];
+        // target: the residual target - base (fine minus coarse forces) when a base is given
+        const int64_t o3 = (src < n_ion) ? 3 * (int64_t)src : 3 * ((int64_t)src - n_ion);
+        const float* tg = ((src < n_ion) ? ion_tgt : wc_tgt) + o3;
+        const float* bs = (src < n_ion) ? ion_base : wc_base;
+        float t0 = tg[0], t1 = tg[1], t2 = tg[2];
+        if (bs) { t0 -= bs[o3]; t1 -= bs[o3 + 1]; t2 -= bs[o3 + 2]; }
+        const float e0 = f0 - t0, e1 = f1 - t1, e2 = f2 - t2;
         lsum += (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
         // dL/d dF = gscale * e (gscale = 2 / (3 n)); dL/dc_k = s_out q (g . T[k, 1:4])
         const float g0 = gscale * e0 * sq, g1 = gscale * e1 * sq, g2 = gscale * e2 * sq;
@@ -416,6 +663,14 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restric
           dC[(size_t)slot * kOut + k] = g0 * t.y + g1 * t.z + g2 * t.w;
         }
       }
+    }
+  }
+  if (st) {
+    mcorr = wave_max_bits(mcorr);
+    mforce = wave_max_bits(mforce);
+    if ((tid & 63) == 0) {
+      if (mcorr) atomicMax(&st->max_corr_bits, mcorr);
+      if (mforce) atomicMax(&st->max_force_bits, mforce);
     }
   }
   if (TRAIN) {

@@ -119,16 +119,57 @@ class Mlp:
                 _ptr(ion_dF), _ptr(wc_dF), 1 if accumulate else 0), self._h)
         return ion_dF, wc_dF
 
-    def train_step(self, box, ion_pos, ion_q, wc_pos, wc_q, ion_tgt, wc_tgt, lr: float, want_grad=False):
+    def train_step(self, box, ion_pos, ion_q, wc_pos, wc_q, ion_tgt, wc_tgt, lr: float, want_grad=False,
+                   ion_base=None, wc_base=None):
+        """One training step; with ion_base / wc_base the targets are
+        target - base (the residual is formed in the kernel)."""
         loss = torch.empty((), dtype=torch.float64, device=self.device)
         grad = torch.empty(N_TRAIN, dtype=torch.float32, device=self.device) if want_grad else None
         with torch.cuda.device(self.device):
             self._bind()
             _lib.check_mlp(_lib.load().dplr_lr_mlp_train_step(
                 self._h, self._box(box), ion_pos.shape[0], _ptr(ion_pos), _ptr(ion_q), wc_pos.shape[0],
-                _ptr(wc_pos), _ptr(wc_q), _ptr(ion_tgt), _ptr(wc_tgt), ctypes.c_float(lr),
-                ctypes.c_void_p(loss.data_ptr()), _ptr(grad)), self._h)
+                _ptr(wc_pos), _ptr(wc_q), _ptr(ion_tgt), _ptr(wc_tgt), _ptr(ion_base), _ptr(wc_base),
+                ctypes.c_float(lr), ctypes.c_void_p(loss.data_ptr()), _ptr(grad)), self._h)
         return loss, grad
+
+    def norm_accumulate(self, box, ion_pos, ion_q, wc_pos, wc_q):
+        with torch.cuda.device(self.device):
+            self._bind()
+            _lib.check_mlp(_lib.load().dplr_lr_mlp_norm_accumulate(
+                self._h, self._box(box), ion_pos.shape[0], _ptr(ion_pos), _ptr(ion_q), wc_pos.shape[0],
+                _ptr(wc_pos), _ptr(wc_q)), self._h)
+
+    def norm_finish(self):
+        with torch.cuda.device(self.device):
+            self._bind()
+            _lib.check_mlp(_lib.load().dplr_lr_mlp_norm_finish(self._h), self._h)
+
+    def set_train_charges(self, charges):
+        arr = np.ascontiguousarray(charges, dtype=np.float32)
+        _lib.check_mlp(_lib.load().dplr_lr_mlp_set_train_charges(self._h, arr.ctypes.data_as(ctypes.c_void_p),
+                                                                  int(arr.size)), self._h)
+
+    def check_charges(self, ion_q, wc_q):
+        with torch.cuda.device(self.device):
+            self._bind()
+            _lib.check_mlp(_lib.load().dplr_lr_mlp_check_charges(self._h, ion_q.shape[0], _ptr(ion_q),
+                                                                  wc_q.shape[0], _ptr(wc_q)), self._h)
+
+    def audit(self, ion_f, ion_ref, wc_f, wc_ref, accumulate=False):
+        with torch.cuda.device(self.device):
+            self._bind()
+            _lib.check_mlp(_lib.load().dplr_lr_mlp_audit(
+                self._h, ion_f.shape[0], _ptr(ion_f), _ptr(ion_ref), wc_f.shape[0], _ptr(wc_f), _ptr(wc_ref),
+                1 if accumulate else 0), self._h)
+
+    def read_stats(self) -> dict:
+        """Guard statistics recorded on the device (synchronises the stream)."""
+        st = _lib.GuardStats()
+        with torch.cuda.device(self.device):
+            self._bind()
+            _lib.check_mlp(_lib.load().dplr_lr_mlp_read_stats(self._h, ctypes.byref(st)), self._h)
+        return {k: getattr(st, k) for k, _ in _lib.GuardStats._fields_}
 
     def descriptor(self, box, ion_pos, ion_q, wc_pos, wc_q):
         n = ion_pos.shape[0] + wc_pos.shape[0]
@@ -165,13 +206,14 @@ def _dev_tensors(sys, device):
     return t(sys.ion_pos), t(sys.ion_q), t(sys.wc_pos), t(sys.wc_q)
 
 
-def residual_targets(sys, coarse: Plan, fine: Plan, device):
-    """Fine-minus-coarse PPPM forces of one system, from the library's plans."""
+def plan_forces(sys, coarse: Plan, fine: Plan, device):
+    """Device inputs of one system and the coarse- and fine-mesh PPPM forces
+    of the library's plans (the residual is formed by the training kernel)."""
     ri, qi, rw, qw = _dev_tensors(sys, device)
     _, fci, fcw, _ = coarse.compute(ri, qi, rw, qw)
     fci, fcw = fci.clone(), fcw.clone()
     _, ffi, ffw, _ = fine.compute(ri, qi, rw, qw)
-    return (ri, qi, rw, qw), (ffi - fci, ffw - fcw), (fci, fcw), (ffi.clone(), ffw.clone())
+    return (ri, qi, rw, qw), (fci, fcw), (ffi.clone(), ffw.clone())
 
 
 def train(boxes, heldout, coarse_mesh: int, fine_mesh: int, coarse_order: int = 5, fine_order: int = 8,
@@ -188,41 +230,37 @@ def train(boxes, heldout, coarse_mesh: int, fine_mesh: int, coarse_order: int = 
     fine.set_box(box)
     if mlp is None:
         mlp = Mlp(cap, device=device)
-    data = [residual_targets(s, coarse, fine, device) for s in boxes]
-    # input normalisation from the training descriptors (host statistics)
-    feats = []
-    for (ri, qi, rw, qw), _, _, _ in data[: min(len(data), 64)]:
-        T, _ = mlp.descriptor(box, ri, qi, rw, qw)
-        Tn = T.double().cpu().numpy()
-        feats.append(np.einsum("nka,nla->nkl", Tn, Tn[:, :4, :]).reshape(Tn.shape[0], -1))
-    D = np.concatenate(feats)
-    params = init_params(seed)
-    params["mu"] = D.mean(0)
-    params["inv_sigma"] = 1.0 / (D.std(0) + 1e-6 * (np.abs(D).max() + 1.0))
-    mlp.set_params(params)
+    data = [plan_forces(s, coarse, fine, device) for s in boxes]
+    mlp.set_params(init_params(seed))
+    # input normalisation from the training descriptors (device sums)
+    for (ri, qi, rw, qw), _, _ in data[: min(len(data), 64)]:
+        mlp.norm_accumulate(box, ri, qi, rw, qw)
+    mlp.norm_finish()
     losses = []
     nsteps = epochs * len(data)
     step = 0
     rng = np.random.default_rng(seed)
     for ep in range(epochs):
         for i in rng.permutation(len(data)):
-            (ri, qi, rw, qw), (ti, tw), _, _ = data[i]
+            (ri, qi, rw, qw), (fci, fcw), (ffi, ffw) = data[i]
             lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / max(1, nsteps)))
-            loss, _ = mlp.train_step(box, ri, qi, rw, qw, ti, tw, lr_t)
+            loss, _ = mlp.train_step(box, ri, qi, rw, qw, ffi, ffw, lr_t, ion_base=fci, wc_base=fcw)
             losses.append(loss)
             step += 1
         if log:
             log(f"epoch {ep}: mean loss {float(torch.stack(losses[-len(data):]).mean()):.4e}")
     losses = [float(x) for x in losses]
-    # held-out evaluation against the fine mesh
-    num_l = num_c = den = 0.0
-    for s in heldout:
-        (ri, qi, rw, qw), (ti, tw), (fci, fcw), (ffi, ffw) = residual_targets(s, coarse, fine, device)
-        di, dw = mlp.forward(box, ri, qi, rw, qw)
-        num_l += float(((di - ti) ** 2).sum() + ((dw - tw) ** 2).sum())
-        num_c += float((ti ** 2).sum() + (tw ** 2).sum())
-        den += float((ffi ** 2).sum() + (ffw ** 2).sum())
-    rep = TrainReport(losses, math.sqrt(num_l / den), math.sqrt(num_c / den), len(boxes), epochs)
+    # held-out relative force error against the fine mesh: the coarse forces
+    # alone, then with the correction (audit sums accumulated over the boxes)
+    held = [plan_forces(s, coarse, fine, device) for s in heldout]
+    for k, ((ri, qi, rw, qw), (fci, fcw), (ffi, ffw)) in enumerate(held):
+        mlp.audit(fci, ffi, fcw, ffw, accumulate=k > 0)
+    rel_coarse = mlp.read_stats()["audit_rel_rmse"]
+    for k, ((ri, qi, rw, qw), (fci, fcw), (ffi, ffw)) in enumerate(held):
+        mlp.forward(box, ri, qi, rw, qw, fci, fcw, accumulate=True)
+        mlp.audit(fci, ffi, fcw, ffw, accumulate=k > 0)
+    rel_learned = mlp.read_stats()["audit_rel_rmse"]
+    rep = TrainReport(losses, rel_learned, rel_coarse, len(boxes), epochs)
     coarse.close()
     fine.close()
     return mlp, rep
@@ -232,7 +270,9 @@ class LearnedCoarse:
     """Coarse-mesh PPPM + network correction, with a guarded fallback to the
     fine mesh.  compute() returns (E, F_ion, F_wc, virial, mode) where mode is
     'learned', 'fine' or 'audit'.  Energy and virial come from the coarse plan
-    in the learned mode (the network corrects forces only)."""
+    in the learned mode (the network corrects forces only).  Every statistic
+    the guard uses is measured on the device (charge check, forward, audit);
+    this class only carries the step counter and the decision."""
 
     def __init__(self, box, coarse: Plan, fine: Plan, mlp: Mlp, guard_cfg: Optional[dict] = None,
                  train_charges=(6.0, 1.0, -8.0)):
@@ -244,9 +284,10 @@ class LearnedCoarse:
                               min_neighbours=0.0, max_neighbours=0.0)
         if guard_cfg:
             self.guard_cfg.update(guard_cfg)
-        self.train_charges = set(float(c) for c in train_charges)
-        self.stats = dict(audit_valid=0, audit_rel_rmse=0.0, steps_since_audit=0, max_correction=0.0,
-                          max_force=0.0, min_neighbours=0.0, max_neighbours=0.0, unseen_charges=0)
+        mlp.set_train_charges(train_charges)
+        self.steps_since_audit = 0
+        self.audited = False
+        self.stats = {}
         self.force_fine = False
 
     def _learned(self, ri, qi, rw, qw):
@@ -254,22 +295,25 @@ class LearnedCoarse:
         self.mlp.forward(self.box, ri, qi, rw, qw, fi, fw, accumulate=True)
         return E, fi, fw, W
 
-    def compute(self, ion_pos, ion_q, wc_pos, wc_q, check_charges: bool = True):
-        if check_charges:
-            qs = torch.unique(torch.cat([ion_q, wc_q])).double().cpu().numpy()
-            self.stats["unseen_charges"] = int(sum(1 for q in qs if float(q) not in self.train_charges))
-        d = _lib.GUARD_FINE if self.force_fine else guard_decide(self.guard_cfg, self.stats)
+    def compute(self, ion_pos, ion_q, wc_pos, wc_q):
+        self.mlp.check_charges(ion_q, wc_q)
+        st = self.mlp.read_stats()
+        st["steps_since_audit"] = self.steps_since_audit
+        st["audit_valid"] = 1 if self.audited else 0
+        self.stats = st
+        d = _lib.GUARD_FINE if self.force_fine else guard_decide(self.guard_cfg, st)
         if d == _lib.GUARD_FINE:
             E, fi, fw, W = self.fine.compute(ion_pos, ion_q, wc_pos, wc_q)
             return E, fi, fw, W, "fine"
         if d == _lib.GUARD_AUDIT:
             Ef, ffi, ffw, Wf = [x.clone() for x in self.fine.compute(ion_pos, ion_q, wc_pos, wc_q)]
             E, fi, fw, W = self._learned(ion_pos, ion_q, wc_pos, wc_q)
-            num = float(((fi - ffi) ** 2).sum() + ((fw - ffw) ** 2).sum())
-            den = float((ffi ** 2).sum() + (ffw ** 2).sum())
-            self.stats.update(audit_valid=1, audit_rel_rmse=math.sqrt(num / den), steps_since_audit=0)
+            self.mlp.audit(fi, ffi, fw, ffw)
+            self.audited = True
+            self.steps_since_audit = 0
+            self.stats = self.mlp.read_stats()
             # the audit's fine result is the one returned
             return Ef, ffi, ffw, Wf, "audit"
-        self.stats["steps_since_audit"] += 1
+        self.steps_since_audit += 1
         E, fi, fw, W = self._learned(ion_pos, ion_q, wc_pos, wc_q)
         return E, fi, fw, W, "learned"

@@ -144,10 +144,125 @@ def test_guard_audits_then_falls_back(torch):
     assert modes[0] == "audit" and modes[1:] == ["fine", "fine"]
     assert lc.stats["audit_rel_rmse"] > 1e-3
     # with a loose tolerance the learned form runs until the next audit is due
-    lc2 = L.LearnedCoarse(s.box, coarse, fine, m, guard_cfg=dict(max_audit_rel_rmse=1.0, audit_interval=3))
+    # (the correction-size trigger off: the untrained network's corrections
+    # are large, which that trigger would rightly reject)
+    lc2 = L.LearnedCoarse(s.box, coarse, fine, m, guard_cfg=dict(max_audit_rel_rmse=1.0, audit_interval=3,
+                                                                  max_correction_ratio=0.0))
     modes2 = [lc2.compute(*args)[4] for _ in range(5)]
     assert modes2 == ["audit", "learned", "learned", "learned", "audit"]
     # unseen charges (Na+ / Cl- are absent from the water training set) force the fine mesh
     q = args[1].clone()
     q[0] = 1.5
     assert lc2.compute(args[0], q, args[2], args[3])[4] == "fine"
+
+
+def test_descriptor_and_forward_bitwise_repeatable(torch, small):
+    """The cell list puts each cell's particles in original-index order, so
+    two calls give bitwise equal descriptors, order and corrections."""
+    from paper_2504_15508_amd import learned as L
+    s = _rounded(systems.training_box(1))
+    m = L.Mlp(s.n)
+    p, mu, isd, _, _ = _params_for(_rounded(small), 3)
+    m.set_params(_pack(p, mu, isd))
+    args = [_t(torch, s.ion_pos), _t(torch, s.ion_q), _t(torch, s.wc_pos), _t(torch, s.wc_q)]
+    T1, o1 = [x.clone() for x in m.descriptor(s.box, *args)]
+    f1 = [x.clone() for x in m.forward(s.box, *args)]
+    T2, o2 = m.descriptor(s.box, *args)
+    f2 = m.forward(s.box, *args)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2) and torch.equal(T1, T2)
+    assert torch.equal(f1[0], f2[0]) and torch.equal(f1[1], f2[1])
+    # within each cell the order is the original index order
+    o = o1.cpu().numpy()
+    assert sorted(o.tolist()) == list(range(s.n))
+
+
+def test_normalisation_and_audit_match_numpy(torch, small):
+    """mu / inv_sigma from the device sums against NumPy on the oracle's
+    invariants; the audit's relative RMSE against NumPy."""
+    from paper_2504_15508_amd import learned as L
+    boxes = [_rounded(systems.training_box(i)) for i in range(3)]
+    m = L.Mlp(max(b.n for b in boxes))
+    m.set_params(L.init_params(0))
+    Ds = []
+    for b in boxes:
+        m.norm_accumulate(b.box, _t(torch, b.ion_pos), _t(torch, b.ion_q), _t(torch, b.wc_pos), _t(torch, b.wc_q))
+        Ds.append(OL.descriptor(b.all_pos(), b.all_q(), b.box)[1])
+    m.norm_finish()
+    got = m.get_params()
+    D = np.concatenate(Ds)
+    mu0 = D.mean(0)
+    isd0 = 1.0 / (D.std(0) + 1e-6 * (np.abs(D).max() + 1.0))
+    emu = np.abs(got["mu"] - mu0).max() / np.abs(mu0).max()
+    eisd = np.abs(got["inv_sigma"] - isd0).max() / np.abs(isd0).max()
+    print(f"normalisation: mu {emu:.2e}, inv_sigma {eisd:.2e}")
+    assert emu < 1e-4 and eisd < 1e-4
+    rng = np.random.default_rng(5)
+    a, b = rng.normal(0, 1, (300, 3)), rng.normal(0, 1, (300, 3))
+    c, d = rng.normal(0, 1, (77, 3)), rng.normal(0, 1, (77, 3))
+    m.audit(_t(torch, a), _t(torch, b), _t(torch, c), _t(torch, d))
+    st = m.read_stats()
+    A, B = np.concatenate([a, c]).astype(np.float32).astype(float), np.concatenate([b, d]).astype(np.float32).astype(float)
+    ref = np.sqrt(((A - B) ** 2).sum() / (B ** 2).sum())
+    assert st["audit_valid"] == 1 and abs(st["audit_rel_rmse"] - ref) <= 1e-12 * ref
+
+
+def test_residual_target_formed_in_kernel(torch, small):
+    """train_step(target = fine, base = coarse) equals train_step on the
+    residual fine - coarse formed outside."""
+    from paper_2504_15508_amd import learned as L
+    s = _rounded(small)
+    p, mu, isd, _, _ = _params_for(s, 5)
+    rng = np.random.default_rng(2)
+    fine, coarse = rng.normal(0, 0.5, (s.n, 3)), rng.normal(0, 0.5, (s.n, 3))
+    m = L.Mlp(s.n)
+    m.set_params(_pack(p, mu, isd))
+    args = [_t(torch, s.ion_pos), _t(torch, s.ion_q), _t(torch, s.wc_pos), _t(torch, s.wc_q)]
+    fi, fw = _t(torch, fine[: s.n_ion]), _t(torch, fine[s.n_ion:])
+    ci, cw = _t(torch, coarse[: s.n_ion]), _t(torch, coarse[s.n_ion:])
+    l1, g1 = m.train_step(s.box, *args, fi, fw, lr=0.0, want_grad=True, ion_base=ci, wc_base=cw)
+    l2, g2 = m.train_step(s.box, *args, fi - ci, fw - cw, lr=0.0, want_grad=True)
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
+
+
+def test_guard_triggers_from_runtime_statistics(torch):
+    """The correction and neighbour triggers fire from statistics the forward
+    measures on the device (no synthetic statistics)."""
+    from paper_2504_15508_amd import learned as L
+    from paper_2504_15508_amd.plan import Plan
+    s = systems.training_box(0)
+    coarse = Plan(16, order=5, precision="fp32", capacity=s.n)
+    fine = Plan(32, order=8, precision="fp32", capacity=s.n)
+    coarse.set_box(s.box)
+    fine.set_box(s.box)
+    m = L.Mlp(s.n)
+    p = L.init_params(0)
+    p["b4"] = np.full(32, 5.0)                # a deliberately large correction
+    m.set_params(p)
+    args = [_t(torch, s.ion_pos), _t(torch, s.ion_q), _t(torch, s.wc_pos), _t(torch, s.wc_q)]
+    # correction trigger: |dF| above 1% of the largest coarse force
+    lc = L.LearnedCoarse(s.box, coarse, fine, m, guard_cfg=dict(max_audit_rel_rmse=1e3, audit_interval=50,
+                                                                 max_correction_ratio=1e-2))
+    modes = [lc.compute(*args)[4] for _ in range(3)]
+    st = lc.stats
+    print(f"runtime stats: max|dF| {st['max_correction']:.3e}, max|F| {st['max_force']:.3e}, "
+          f"neighbours {st['min_neighbours']:.0f}..{st['max_neighbours']:.0f}, modes {modes}")
+    assert st["max_correction"] > 1e-2 * st["max_force"] > 0
+    assert modes == ["audit", "fine", "fine"]
+    # neighbour trigger: a lower bound above the measured minimum count
+    # (fresh networks: the statistics of a network persist between calls)
+    lo = st["min_neighbours"]
+    m2 = L.Mlp(s.n)
+    m2.set_params(L.init_params(0))
+    lc2 = L.LearnedCoarse(s.box, coarse, fine, m2, guard_cfg=dict(max_audit_rel_rmse=1e3, audit_interval=50,
+                                                                   max_correction_ratio=0.0,
+                                                                   min_neighbours=lo + 1.0))
+    modes2 = [lc2.compute(*args)[4] for _ in range(2)]
+    assert modes2 == ["audit", "fine"]
+    # and with the bound at the measured minimum the learned form runs
+    m3 = L.Mlp(s.n)
+    m3.set_params(L.init_params(0))
+    lc3 = L.LearnedCoarse(s.box, coarse, fine, m3, guard_cfg=dict(max_audit_rel_rmse=1e3, audit_interval=50,
+                                                                   max_correction_ratio=0.0, min_neighbours=lo))
+    assert [lc3.compute(*args)[4] for _ in range(2)] == ["audit", "learned"]
