@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the order-8 and accuracy legs")
     ap.add_argument("--eager-only", action="store_true", help="no graph capture (profiling runs)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned coarse-mesh leg")
+    ap.add_argument("--no-config5", action="store_true", help="skip the 1.2M-charge config-5 leg")
     ap.add_argument("--learned-boxes", type=int, default=2000, help="training boxes for the learned leg")
     ap.add_argument("--learned-epochs", type=int, default=3)
     ap.add_argument("--copy-ref-mb", type=float, default=0.0,
@@ -716,7 +717,7 @@ def main():
         except Exception as e:
             extras["learned_error"] = repr(e)
 
-    if not args.no_learned and not args.eager_only:
+    if not args.no_learned and not args.no_config5 and not args.eager_only:
         try:
             log("config-5 leg: 1,206,000 charges, 256^3 plain vs 128^3 + network")
             extras.update(config5_leg(args, dev, timed_graph))

@@ -68,6 +68,15 @@ static_assert(DPLR_SORT_CHUNKS >= 1 && DPLR_SORT_CHUNKS <= 256, "sort chunk coun
 #ifndef DPLR_IXY_AD_THREADS
 #define DPLR_IXY_AD_THREADS 64
 #endif
+#ifndef DPLR_MIXED_QSHIFT
+#define DPLR_MIXED_QSHIFT 4
+#endif
+#ifndef DPLR_MIXED_FUSED
+#define DPLR_MIXED_FUSED 1
+#endif
+#ifndef DPLR_MIXED_ZCOLS
+#define DPLR_MIXED_ZCOLS 16
+#endif
 #ifndef DPLR_FFTZ_COLS
 #define DPLR_FFTZ_COLS 8
 #endif
@@ -76,8 +85,8 @@ constexpr int kMinMesh = 16;
 constexpr int kMaxMesh = 512;
 constexpr int kMaxOrder = 8;
 constexpr int kMinOrder = 2;
-constexpr int kMaxQ32Mesh = 256;
-constexpr int64_t kMixedSplitMinParticles = 65536;  // split plane spread from this many particles  // int32-quantised transforms are direct sums, O(K) per output
+constexpr int kMaxQ32Mesh = 256;  // int32-quantised transforms are direct sums, O(K) per output
+constexpr int64_t kMixedSplitMinParticles = 65536;  // split plane spread from this many particles
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -168,6 +177,9 @@ struct dplr_lr_plan_s {
   void* mrec = nullptr;       // ... per-particle stencil offsets and charge (plane spread)
   int* mspk = nullptr;        // ... per-particle packed stencil starts (plane spread)
   int msplit = 1;             // ... particle ranges per plane of the split plane spread (partials in mmesh)
+  size_t mfused = 0;          // ... LDS of the fused plane kernels (0: the per-axis transforms)
+  int mzc = 1;                // ... columns per block of the fused z pass
+  int mzblk = 0;              // ... blocks (and partials) of the fused z pass
   int q32_nodes[3] = {0, 0, 0};  // int32-quantised transforms: node blocks per axis (0: off)
   double q32_scale = 0.0;
   unsigned long long* q32_clamped = nullptr;  // saturated partial values of the last compute
@@ -616,9 +628,12 @@ void launch_mixed_fft(dplr_lr_plan p, cpx<T>* data, int ncomp, int sign, T* pack
     int C = 1;
     if (a > 0)
       while (C < 16 && stride[a] % (2 * C) == 0 && 2 * (size_t)C * K[a] * sizeof(cpx<T>) <= 32768) C *= 2;
+    else  // x rows: several consecutive rows per block, at most about 256 threads' work
+      while (C < 16 && rows % (2 * C) == 0 && 2 * C * K[a] <= 1024 && 2 * (size_t)C * K[a] * sizeof(cpx<T>) <= 32768)
+        C *= 2;
     const int thr = std::min(256, std::max(64, (C * K[a] / 2 + 63) / 64 * 64));
     hipLaunchKernelGGL(k_mixed_fft_axis<T>, dim3((unsigned)(rows / C), (unsigned)ncomp), dim3(thr),
-                       2 * sizeof(cpx<T>) * C * K[a], p->stream, data, K[a], stride[a], ntot, sign,
+                       (2 * C + 1) * sizeof(cpx<T>) * K[a], p->stream, data, K[a], stride[a], ntot, sign,
                        a == 2 ? packed : (T*)nullptr, C);
   }
 }
@@ -652,20 +667,47 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
   const bool q32 = p->q32_nodes[0] > 0;
   // spread: one thread per (particle, stencil plane); gather: 256 / P particles per block
   const unsigned nbp = (unsigned)((n * P + 255) / 256);
-  const unsigned nbg = (unsigned)((n + 256 / P - 1) / (256 / P));
+  const int nchg = (int)((n + mixed_gather_per_block<P>() - 1) / mixed_gather_per_block<P>());  // gather chunks; grid a multiple of the XCDs
+  const unsigned nbg = (unsigned)((nchg + kNumXcd - 1) / kNumXcd * kNumXcd);
+  // split the particles over S blocks per plane when the planes alone
+  // leave most compute units idle and there are enough particles
+  // fused plane kernels (not for the int32 transforms, which run per axis)
+  const bool fused = p->mfused > 0 && !q32;
+  const int S = n >= kMixedSplitMinParticles ? p->msplit : 1;
+  const int npart = fused ? p->mzblk : p->mblk;  // energy/virial block partials of this call
   if (p->lds_mplane) {
-    // one block per z plane: spread in LDS, written straight into the spectrum buffer
+    // counting sort by (particle split, stencil-start plane) with the plane
+    // kernels' sort, then one block per (z plane, split): spread in LDS,
+    // written straight into the spectrum buffer (or integer partial planes)
     ProfScope ps(p, 11);
-    if (n > 0)
-      hipLaunchKernelGGL((k_mixed_prep<T, P>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                         (const T*)ion_pos, (const T*)ion_q, (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0],
-                         ih[1], ih[2], g.K[0], g.K[1], g.K[2], (T4<T>*)p->mrec, p->mspk);
-    // split the particles over S blocks per plane when the planes alone
-    // leave most compute units idle and there are enough particles
-    const int S = n >= kMixedSplitMinParticles ? p->msplit : 1;
-    hipLaunchKernelGGL((k_mixed_spread_plane<T, P>), dim3(g.K[2], S), dim3(1024), p->lds_mplane, s,
-                       (const T4<T>*)p->mrec, (const int*)p->mspk, n, g.K[0], g.K[1], g.K[2], spec, p->mmesh);
-    if (S > 1)
+    Geo gs = g;
+    gs.nsplit = S;
+    gs.nbins = S * g.K[2] * g.NQ;
+    const int64_t ca = DPLR_SORT_CHUNK_ALIGN;
+    const int64_t chunk = std::max<int64_t>(ca, ((n + p->max_chunks - 1) / p->max_chunks + ca - 1) / ca * ca);
+    const int nblk = (int)((n + chunk - 1) / chunk);
+    const size_t lds = sizeof(int) * gs.nbins;
+    if (n > 0) {
+      hipLaunchKernelGGL((k_bin_hist<T, P>), dim3(nblk), dim3(1024), lds, s, (const T*)ion_pos, (const T*)wc_pos,
+                         n_ion, n, ih[0], ih[1], ih[2], p->bin_hist, (int)chunk, gs);
+      hipLaunchKernelGGL(k_bin_colscan, dim3((gs.nbins + 63) / 64), dim3(1024), 0, s, p->bin_hist, p->bin_count,
+                         nblk, gs.nbins);
+      hipLaunchKernelGGL((k_bin_place<T, P>), dim3(nblk), dim3(1024), 2 * lds, s, (const T*)ion_pos,
+                         (const T*)wc_pos, (const T*)ion_q, (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2],
+                         p->bin_hist, p->bin_count, p->bin_start, (T4<T>*)p->mrec, p->mspk, p->perm, p->qmax,
+                         (int)chunk, gs);
+    } else {
+      hipLaunchKernelGGL(k_fill_int, dim3((gs.nbins + 1 + 255) / 256), dim3(256), 0, s, p->bin_start, gs.nbins + 1,
+                         0);
+    }
+    if (fused)
+      hipLaunchKernelGGL((k_mixed_spread_xy<T, P>), dim3(g.K[2], S), dim3(1024), p->mfused, s,
+                         (const T4<T>*)p->mrec, (const int*)p->mspk, (const int*)p->bin_start, gs,
+                         reinterpret_cast<cpx<T>*>(p->mmesh));
+    else
+      hipLaunchKernelGGL((k_mixed_spread_sorted<T, P>), dim3(g.K[2], S), dim3(1024), p->lds_mplane, s,
+                         (const T4<T>*)p->mrec, (const int*)p->mspk, (const int*)p->bin_start, gs, spec, p->mmesh);
+    if (S > 1 && !fused)
       hipLaunchKernelGGL(k_mixed_combine<T>, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s,
                          (const long long*)p->mmesh, S, ntot, spec);
   } else if (n > 0) {
@@ -678,7 +720,7 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
     // the saturation count of this call starts at zero (a fill kernel, not a memset)
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(p->q32_clamped), 2, 0);
   }
-  {
+  if (!fused) {
     ProfScope ps(p, 12);
     if (!p->lds_mplane)
       hipLaunchKernelGGL(k_mixed_unfix<T>, dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, s, p->mmesh, spec,
@@ -693,25 +735,44 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
   const bool want_virial = !(p->cfg.flags & DPLR_LR_NO_VIRIAL) && virial;
   {
     ProfScope ps(p, 13);
-    hipLaunchKernelGGL(k_mixed_poisson<T>, dim3((unsigned)p->mblk), dim3(256), 0, s, spec, field, p->G, g.K[0],
-                       g.K[1], g.K[2], pc, q32 ? p->cfg.coulomb_k / V : 1.0, p->partials);
+    if (fused) {
+      const int C = p->mzc;
+      hipLaunchKernelGGL(k_mixed_fftz_poisson<T>, dim3((unsigned)p->mzblk), dim3(kFusedZThreads),
+                         (size_t)(2 * C + 1) * g.K[2] * sizeof(cpx<T>), s, (const cpx<T>*)p->mmesh, S, field,
+                         field + ntot, p->G, g.K[0], g.K[1], g.K[2], C, pc, 1.0, p->partials);
+    } else {
+      hipLaunchKernelGGL(k_mixed_poisson<T>, dim3((unsigned)p->mblk), dim3(256), 0, s, spec, field, p->G, g.K[0],
+                         g.K[1], g.K[2], pc, q32 ? p->cfg.coulomb_k / V : 1.0, p->partials);
+    }
     // with particles, block 0 of the gather reduces the partials instead
     if (n == 0)
-      hipLaunchKernelGGL(k_mixed_reduce, dim3(1), dim3(256), 0, s, (const double*)p->partials, p->mblk,
+      hipLaunchKernelGGL(k_mixed_reduce, dim3(1), dim3(256), 0, s, (const double*)p->partials, npart,
                          p->cfg.coulomb_k / (2.0 * V), energy, want_virial ? virial : (double*)nullptr);
   }
   if (n > 0) {
     {
       ProfScope ps(p, 14);
-      if (q32) launch_mixed_dft_q32<T>(p, field, 3, +1, (T*)p->mpacked);
+      if (fused)
+        hipLaunchKernelGGL(k_mixed_ifft_xy<T>, dim3(g.K[2], 2), dim3(1024), p->mfused, s, (const cpx<T>*)field,
+                           (const cpx<T>*)(field + ntot), g.K[0], g.K[1], (T*)p->mpacked);
+      else if (q32) launch_mixed_dft_q32<T>(p, field, 3, +1, (T*)p->mpacked);
       else launch_mixed_fft<T>(p, field, 3, +1, (T*)p->mpacked);
     }
     ProfScope ps(p, 15);
-    hipLaunchKernelGGL((k_mixed_gather<T, P>), dim3(nbg), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
-                       (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], g.K[0], g.K[1], g.K[2],
-                       (const T4<T>*)p->mpacked, (T*)ion_force, (T*)wc_force, q32 ? (T)1 : (T)(p->cfg.coulomb_k / V),
-                       (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0, (const double*)p->partials, p->mblk,
-                       p->cfg.coulomb_k / (2.0 * V), energy, want_virial ? virial : (double*)nullptr);
+    if (p->lds_mplane)  // the sorted records of the spread
+      hipLaunchKernelGGL((k_mixed_gather_sorted<T, P>), dim3(nbg), dim3(256), 0, s, (const T4<T>*)p->mrec,
+                         (const int*)p->mspk, (const int*)p->perm, n_ion, n, g.K[0], g.K[1], g.K[2],
+                         (const T4<T>*)p->mpacked, (T*)ion_force, (T*)wc_force,
+                         q32 ? (T)1 : (T)(p->cfg.coulomb_k / V), (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0,
+                         (const double*)p->partials, npart, p->cfg.coulomb_k / (2.0 * V), energy,
+                         want_virial ? virial : (double*)nullptr, nchg);
+    else
+      hipLaunchKernelGGL((k_mixed_gather<T, P>), dim3(nbg), dim3(256), 0, s, (const T*)ion_pos, (const T*)ion_q,
+                         (const T*)wc_pos, (const T*)wc_q, n_ion, n, ih[0], ih[1], ih[2], g.K[0], g.K[1], g.K[2],
+                         (const T4<T>*)p->mpacked, (T*)ion_force, (T*)wc_force,
+                         q32 ? (T)1 : (T)(p->cfg.coulomb_k / V), (p->cfg.flags & DPLR_LR_ACCUMULATE) ? 1 : 0,
+                         (const double*)p->partials, npart, p->cfg.coulomb_k / (2.0 * V), energy,
+                         want_virial ? virial : (double*)nullptr, nchg);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
@@ -842,16 +903,37 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
     dplr_lr_status sm = DPLR_LR_OK;
     void* tmp = nullptr;
     // particle ranges per plane of the split plane spread: enough blocks for 256 CUs, at most 8
-    p->msplit = std::max(1, std::min(8, 256 / g.K[2]));
+    // (a power of two: the sort assigns particles to splits by index bits)
+    p->msplit = 1;
+    while (2 * p->msplit <= std::min(8, 256 / g.K[2])) p->msplit *= 2;
+    // fused z pass: C (x, y) columns per block, a power of two dividing Kx Ky,
+    // at most 16 and C Kz <= kFusedZMaxPts
+    const size_t nxy = (size_t)g.K[0] * g.K[1];
+    while (p->mzc < DPLR_MIXED_ZCOLS && nxy % (2 * p->mzc) == 0 && 2 * (size_t)p->mzc * g.K[2] <= (size_t)kFusedZMaxPts)
+      p->mzc *= 2;
+    p->mzblk = (int)(nxy / p->mzc);
+    // the sort's bins: one per (split, stencil-start plane, group of
+    // 2^qshift stencil-start rows); columns are not binned
+    g.qshift = DPLR_MIXED_QSHIFT;
+    g.NQ = (g.K[1] + (1 << g.qshift) - 1) >> g.qshift;
+    g.split_by_index = 1;
+    g.nsplit = p->msplit;
+    g.xs = g.K[0];
+    g.nbins = p->msplit * g.K[2] * g.NQ;
     if (sm == DPLR_LR_OK) {
-      sm = alloc(p, &tmp, sizeof(long long) * ntot * p->msplit, "mixed-radix mesh (or split partial meshes)");
+      // integer partial meshes, or the split spectra of the fused spread
+      sm = alloc(p, &tmp, std::max(sizeof(long long), cs) * ntot * p->msplit,
+                 "mixed-radix mesh (or split partial meshes)");
       p->mmesh = (long long*)tmp;
     }
     if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mspec, cs * ntot, "mixed-radix spectrum"); }
     if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mfield, 3 * cs * ntot, "mixed-radix field spectra"); }
     if (sm == DPLR_LR_OK) { sm = alloc(p, &p->mpacked, 4 * ts * ntot, "mixed-radix fields"); }
     if (sm == DPLR_LR_OK) { sm = alloc(p, &tmp, sizeof(double) * ng, "influence"); p->G = (double*)tmp; }
-    if (sm == DPLR_LR_OK) { sm = alloc(p, &tmp, sizeof(double) * 8 * p->mblk, "partials"); p->partials = (double*)tmp; }
+    if (sm == DPLR_LR_OK) {
+      sm = alloc(p, &tmp, sizeof(double) * 8 * std::max(p->mblk, p->mzblk), "partials");
+      p->partials = (double*)tmp;
+    }
     if (sm == DPLR_LR_OK) {
       sm = alloc(p, &tmp, sizeof(unsigned long long), "int32 saturation count");
       p->q32_clamped = (unsigned long long*)tmp;
@@ -873,20 +955,53 @@ dplr_lr_status dplr_lr_plan_create(const dplr_lr_config* cfg, void* hip_stream, 
     if (lp + 10240 <= p->lds_budget) {
       const void* f = nullptr;
       switch (cfg->order) {
-#define DPLR_PLANE(PP)                                                                                     \
-  case PP:                                                                                                 \
-    f = p->fp64 ? (const void*)k_mixed_spread_plane<double, PP> : (const void*)k_mixed_spread_plane<float, PP>; \
+#define DPLR_PLANE(PP)                                                                                       \
+  case PP:                                                                                                   \
+    f = p->fp64 ? (const void*)k_mixed_spread_sorted<double, PP> : (const void*)k_mixed_spread_sorted<float, PP>; \
     break;
         DPLR_PLANE(2) DPLR_PLANE(3) DPLR_PLANE(4) DPLR_PLANE(5) DPLR_PLANE(6) DPLR_PLANE(7) DPLR_PLANE(8)
 #undef DPLR_PLANE
       }
       p->lds_mplane = lp;
       if (lp > 65536 && !raise_lds_limit(f, lp)) p->lds_mplane = 0;
+      // fused plane kernels when an xy plane of complex values (and its roots
+      // of unity) fits in LDS
+      const size_t lf = (nxy + g.K[0] + g.K[1]) * cs;
+      const size_t lz = (size_t)(2 * p->mzc + 1) * g.K[2] * cs;
+      const size_t fmax = p->fp64 ? FusedPlane<double>::kMaxPts : FusedPlane<float>::kMaxPts;
+      if (DPLR_MIXED_FUSED && p->lds_mplane && nxy <= fmax && lf + 2048 <= p->lds_budget) {
+        const void* fs = nullptr;
+        switch (cfg->order) {
+#define DPLR_FUSED(PP)                                                                                   \
+  case PP:                                                                                               \
+    fs = p->fp64 ? (const void*)k_mixed_spread_xy<double, PP> : (const void*)k_mixed_spread_xy<float, PP>; \
+    break;
+          DPLR_FUSED(2) DPLR_FUSED(3) DPLR_FUSED(4) DPLR_FUSED(5) DPLR_FUSED(6) DPLR_FUSED(7) DPLR_FUSED(8)
+#undef DPLR_FUSED
+        }
+        const void* fi = p->fp64 ? (const void*)k_mixed_ifft_xy<double> : (const void*)k_mixed_ifft_xy<float>;
+        const void* fzk = p->fp64 ? (const void*)k_mixed_fftz_poisson<double> : (const void*)k_mixed_fftz_poisson<float>;
+        if (raise_lds_limit(fs, lf) && raise_lds_limit(fi, lf) && (lz <= 60000 || raise_lds_limit(fzk, lz)))
+          p->mfused = lf;
+      }
       const size_t capn = (size_t)std::max<int64_t>(cfg->capacity, 1);
       void* t2 = nullptr;
       dplr_lr_status sr = DPLR_LR_OK;
       if (p->lds_mplane) sr = alloc(p, &p->mrec, 4 * ts * capn, "mixed-radix stencil records");
       if (p->lds_mplane && sr == DPLR_LR_OK) { sr = alloc(p, &t2, sizeof(int) * capn, "mixed-radix stencil starts"); p->mspk = (int*)t2; }
+      // the counting sort's buffers (bins of every split count up to msplit)
+      const size_t nb1 = (size_t)p->geo.nbins + 1;
+      if (p->lds_mplane && sr == DPLR_LR_OK) { sr = alloc(p, &t2, sizeof(int) * capn, "perm"); p->perm = (int*)t2; }
+      if (p->lds_mplane && sr == DPLR_LR_OK) { sr = alloc(p, &t2, sizeof(int) * nb1, "bin_count"); p->bin_count = (int*)t2; }
+      if (p->lds_mplane && sr == DPLR_LR_OK) { sr = alloc(p, &t2, sizeof(int) * nb1, "bin_start"); p->bin_start = (int*)t2; }
+      if (p->lds_mplane && sr == DPLR_LR_OK) {
+        sr = alloc(p, &t2, sizeof(int) * (size_t)p->max_chunks * p->geo.nbins, "bin histograms");
+        p->bin_hist = (int*)t2;
+      }
+      if (p->lds_mplane && sr == DPLR_LR_OK) {
+        sr = alloc(p, &t2, sizeof(unsigned) * (size_t)p->max_chunks, "charge maxima");
+        p->qmax = (unsigned*)t2;
+      }
       if (sr != DPLR_LR_OK) {
         set_global_error(p->err);
         free_all(p);

@@ -37,10 +37,12 @@ def test_paper_grids(torch_dev, mesh, precision):
 
 
 # (160, 135, 8) and (240, 90, 10): xy planes too large for LDS, so the
-# spread takes the global-atomic kernel instead of the plane kernel
+# spread takes the global-atomic kernel instead of the plane kernel;
+# (120, 100, 12): the plane of 64-bit accumulators fits in LDS but the FP64
+# complex plane of the fused transforms does not (per-axis transforms)
 @pytest.mark.parametrize("mesh,order", [((15, 25, 27), 3), ((45, 30, 20), 7), ((8, 8, 8), 5), ((9, 10, 6), 6),
                                         ((6, 5, 4), 4), ((96, 80, 75), 5), ((160, 135, 8), 5), ((240, 90, 10), 4),
-                                        ((480, 18, 20), 5), ((12, 500, 9), 3)])
+                                        ((480, 18, 20), 5), ((12, 500, 9), 3), ((120, 100, 12), 5)])
 def test_mixed_sizes_fp64(torch_dev, mesh, order):
     s = systems.water_box(512, 25.0, seed=20261129, name="water512_25A")
     s.box = np.array([25.0, 27.5, 23.0])
@@ -51,6 +53,19 @@ def test_mixed_sizes_fp64(torch_dev, mesh, order):
 def test_mixed_sizes_fp32(torch_dev, mesh):
     s = systems.workload(2).system()
     check_vs_pppm(torch_dev, s, mesh, 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_split_plane_spectra(torch_dev, precision):
+    # 68,000 charges: enough for the plane spread to split every plane's
+    # particles over several blocks (Kz = 36: four splits), whose partial
+    # spectra the z pass adds; odd-length y rows (45 = 3^2 5) and C = 8
+    # columns per z block (Kx Ky = 1800)
+    s = systems.water_box(17000, 82.0, seed=20261203, name="water17000_82A")
+    if precision == "fp64":
+        check_vs_pppm(torch_dev, s, (40, 45, 36), 5, "fp64", 1e-9, 1e-9, 1e-9)
+    else:
+        check_vs_pppm(torch_dev, s, (40, 45, 36), 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
 
 
 def test_refined_mixed_mesh_meets_ewald(torch_dev):
