@@ -291,6 +291,18 @@ dplr_lr_status dplr_lr_mlp_set_stream(dplr_lr_mlp m, void* hip_stream);
 /* Host copies of the packed parameters (synchronous); set_params resets the Adam state. */
 dplr_lr_status dplr_lr_mlp_set_params(dplr_lr_mlp m, const float* host_params, int64_t count);
 dplr_lr_status dplr_lr_mlp_get_params(dplr_lr_mlp m, float* host_params, int64_t count);
+/* Checkpoint and resume of training: the whole training state as one byte
+ * blob of dplr_lr_mlp_state_bytes() bytes in caller-owned host memory
+ * (header with a magic, version and sizes; the packed parameters; the Adam
+ * first and second moments and step count; the normalisation sums being
+ * accumulated; the set of training charges).  Both calls are synchronous on
+ * the network's stream.  set_state returns E_INVALID, changing nothing, for a
+ * blob of another size, magic or version, or from a network with another
+ * cutoff or output scale.  A step after set_state continues exactly (bitwise)
+ * the training that get_state saved. */
+int64_t dplr_lr_mlp_state_bytes(void);
+dplr_lr_status dplr_lr_mlp_get_state(dplr_lr_mlp m, void* host_state, int64_t bytes);
+dplr_lr_status dplr_lr_mlp_set_state(dplr_lr_mlp m, const void* host_state, int64_t bytes);
 /* dF for every particle, written (accumulate = 0) or added (accumulate != 0)
  * to ion_dF / wc_dF.  The first call for a larger box grows the cell list
  * (device allocation); later calls allocate nothing.  Neighbours are taken in

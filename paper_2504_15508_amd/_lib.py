@@ -28,7 +28,8 @@ EXPORTS = [
     "dplr_lr_debug_dft_q32",
     "dplr_lr_profile_enable", "dplr_lr_profile_read", "dplr_lr_profile_stage_name",
     "dplr_lr_mlp_config_default", "dplr_lr_mlp_param_count", "dplr_lr_mlp_create", "dplr_lr_mlp_destroy",
-    "dplr_lr_mlp_set_stream", "dplr_lr_mlp_set_params", "dplr_lr_mlp_get_params", "dplr_lr_mlp_forward",
+    "dplr_lr_mlp_set_stream", "dplr_lr_mlp_set_params", "dplr_lr_mlp_get_params",
+    "dplr_lr_mlp_state_bytes", "dplr_lr_mlp_get_state", "dplr_lr_mlp_set_state", "dplr_lr_mlp_forward",
     "dplr_lr_mlp_train_step", "dplr_lr_mlp_descriptor", "dplr_lr_mlp_last_error", "dplr_lr_guard_decide",
     "dplr_lr_mlp_norm_accumulate", "dplr_lr_mlp_norm_finish", "dplr_lr_mlp_set_train_charges",
     "dplr_lr_mlp_check_charges", "dplr_lr_mlp_audit", "dplr_lr_mlp_read_stats",
@@ -106,6 +107,9 @@ def load():
         "dplr_lr_mlp_set_stream": ([p, p], ctypes.c_int),
         "dplr_lr_mlp_set_params": ([p, p, i64], ctypes.c_int),
         "dplr_lr_mlp_get_params": ([p, p, i64], ctypes.c_int),
+        "dplr_lr_mlp_state_bytes": ([], i64),
+        "dplr_lr_mlp_get_state": ([p, p, i64], ctypes.c_int),
+        "dplr_lr_mlp_set_state": ([p, p, i64], ctypes.c_int),
         "dplr_lr_mlp_forward": ([p, ctypes.POINTER(d), i64, p, p, i64, p, p, p, p, i32], ctypes.c_int),
         "dplr_lr_mlp_train_step": ([p, ctypes.POINTER(d), i64, p, p, i64, p, p, p, p, p, p, ctypes.c_float, p, p],
                                    ctypes.c_int),

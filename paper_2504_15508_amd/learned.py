@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import json
 import math
 from typing import Optional
 
@@ -101,6 +102,26 @@ class Mlp:
             _lib.check_mlp(_lib.load().dplr_lr_mlp_get_params(self._h, vec.ctypes.data_as(ctypes.c_void_p),
                                                                 vec.size), self._h)
         return unpack(vec)
+
+    def get_state(self) -> np.ndarray:
+        """The whole training state (parameters, Adam moments and step count,
+        normalisation sums, training charges) as a uint8 array."""
+        lib = _lib.load()
+        blob = np.zeros(int(lib.dplr_lr_mlp_state_bytes()), dtype=np.uint8)
+        with torch.cuda.device(self.device):
+            self._bind()
+            _lib.check_mlp(lib.dplr_lr_mlp_get_state(self._h, blob.ctypes.data_as(ctypes.c_void_p), blob.size),
+                           self._h)
+        return blob
+
+    def set_state(self, blob):
+        """Restores a state from get_state (training then continues bitwise
+        as it would have)."""
+        blob = np.ascontiguousarray(blob, dtype=np.uint8)
+        with torch.cuda.device(self.device):
+            self._bind()
+            _lib.check_mlp(_lib.load().dplr_lr_mlp_set_state(self._h, blob.ctypes.data_as(ctypes.c_void_p),
+                                                               blob.size), self._h)
 
     @staticmethod
     def _box(box):
@@ -218,9 +239,18 @@ def plan_forces(sys, coarse: Plan, fine: Plan, device):
 
 def train(boxes, heldout, coarse_mesh: int, fine_mesh: int, coarse_order: int = 5, fine_order: int = 8,
           epochs: int = 4, lr: float = 2e-3, seed: int = 0, mlp: Optional[Mlp] = None,
-          device: Optional[torch.device] = None, log=None) -> tuple:
+          device: Optional[torch.device] = None, log=None, checkpoint: Optional[str] = None,
+          resume: Optional[str] = None, stop_after: Optional[int] = None) -> tuple:
     """Train the correction on seeded boxes (list of systems.System, same box).
-    Returns (mlp, TrainReport)."""
+    Returns (mlp, TrainReport).
+
+    checkpoint: path of a .npz file rewritten at the end of every epoch with
+    the network's training state (parameters, Adam moments and step count,
+    normalisation), the epoch and step counters, the losses so far and the
+    state of the generator that orders the boxes.  resume: such a file to
+    continue from, with the same boxes, epochs, lr and seed; the result is
+    bitwise that of an uninterrupted run.  stop_after: run at most this many
+    epochs in this call (a time slice of a longer run)."""
     device = torch.device(device) if device is not None else torch.device("cuda", 0)
     box = boxes[0].box
     cap = max(s.n for s in list(boxes) + list(heldout))
@@ -231,25 +261,41 @@ def train(boxes, heldout, coarse_mesh: int, fine_mesh: int, coarse_order: int = 
     if mlp is None:
         mlp = Mlp(cap, device=device)
     data = [plan_forces(s, coarse, fine, device) for s in boxes]
-    mlp.set_params(init_params(seed))
-    # input normalisation from the training descriptors (device sums)
-    for (ri, qi, rw, qw), _, _ in data[: min(len(data), 64)]:
-        mlp.norm_accumulate(box, ri, qi, rw, qw)
-    mlp.norm_finish()
-    losses = []
     nsteps = epochs * len(data)
-    step = 0
     rng = np.random.default_rng(seed)
-    for ep in range(epochs):
+    run = dict(seed=seed, epochs=epochs, lr=lr, nboxes=len(data))
+    if resume is not None:
+        with np.load(resume, allow_pickle=False) as ck:
+            for k, v in run.items():
+                if type(v)(ck[k]) != v:
+                    raise ValueError(f"checkpoint {resume} is from a run with {k}={ck[k]}, not {v}")
+            mlp.set_state(ck["mlp_state"])
+            ep0, step = int(ck["epoch"]), int(ck["step"])
+            rng.bit_generator.state = json.loads(str(ck["rng_state"]))
+            losses = [float(x) for x in ck["losses"]]
+    else:
+        mlp.set_params(init_params(seed))
+        # input normalisation from the training descriptors (device sums)
+        for (ri, qi, rw, qw), _, _ in data[: min(len(data), 64)]:
+            mlp.norm_accumulate(box, ri, qi, rw, qw)
+        mlp.norm_finish()
+        ep0, step, losses = 0, 0, []
+    ep1 = epochs if stop_after is None else min(epochs, ep0 + int(stop_after))
+    for ep in range(ep0, ep1):
+        ep_losses = []
         for i in rng.permutation(len(data)):
             (ri, qi, rw, qw), (fci, fcw), (ffi, ffw) = data[i]
             lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / max(1, nsteps)))
             loss, _ = mlp.train_step(box, ri, qi, rw, qw, ffi, ffw, lr_t, ion_base=fci, wc_base=fcw)
-            losses.append(loss)
+            ep_losses.append(loss)
             step += 1
+        losses += [float(x) for x in ep_losses]
         if log:
-            log(f"epoch {ep}: mean loss {float(torch.stack(losses[-len(data):]).mean()):.4e}")
-    losses = [float(x) for x in losses]
+            log(f"epoch {ep}: mean loss {float(np.mean(losses[-len(data):])):.4e}")
+        if checkpoint is not None:
+            with open(checkpoint, "wb") as f:
+                np.savez(f, mlp_state=mlp.get_state(), epoch=ep + 1, step=step,
+                         rng_state=json.dumps(rng.bit_generator.state), losses=np.asarray(losses), **run)
     # held-out relative force error against the fine mesh: the coarse forces
     # alone, then with the correction (audit sums accumulated over the boxes)
     held = [plan_forces(s, coarse, fine, device) for s in heldout]

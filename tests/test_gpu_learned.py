@@ -127,6 +127,40 @@ def test_training_beats_coarse_mesh_on_heldout(torch):
     assert rep.heldout_rel_rmse_learned < rep.heldout_rel_rmse_coarse
 
 
+def test_checkpoint_resume_is_bitwise(torch, tmp_path):
+    # an interrupted run (one epoch, checkpoint, a fresh network resumed from
+    # the file) ends bitwise where the uninterrupted run ends: parameters,
+    # Adam moments and step count, and the order of the boxes
+    from paper_2504_15508_amd import learned as L
+    boxes = [systems.training_box(i) for i in range(6)]
+    held = [systems.training_box(0, heldout=True)]
+    kw = dict(coarse_mesh=16, fine_mesh=32, epochs=3, lr=3e-3, seed=7)
+    mlp_a, rep_a = L.train(boxes, held, **kw)
+    ck = str(tmp_path / "ck.npz")
+    _, rep_1 = L.train(boxes, held, checkpoint=ck, stop_after=1, **kw)
+    assert len(rep_1.losses) == len(boxes)
+    mlp_b, rep_b = L.train(boxes, held, resume=ck, checkpoint=ck, **kw)
+    assert rep_b.losses == rep_a.losses
+    sa, sb = mlp_a.get_state(), mlp_b.get_state()
+    assert np.array_equal(sa, sb)
+    assert rep_b.heldout_rel_rmse_learned == rep_a.heldout_rel_rmse_learned
+    # the state blob round-trips, and foreign or damaged blobs are refused
+    mlp_c = L.Mlp(mlp_a.cfg.capacity)
+    mlp_c.set_state(sa)
+    assert np.array_equal(mlp_c.get_state(), sa)
+    bad = sa.copy()
+    bad[0] ^= 0xFF
+    with pytest.raises(RuntimeError, match="magic"):
+        mlp_c.set_state(bad)
+    with pytest.raises(RuntimeError, match="bytes"):
+        mlp_c.set_state(sa[:-1])
+    mlp_d = L.Mlp(mlp_a.cfg.capacity, cutoff=3.5)
+    with pytest.raises(RuntimeError, match="cutoff"):
+        mlp_d.set_state(sa)
+    with pytest.raises(ValueError, match="seed"):
+        L.train(boxes, held, resume=ck, **{**kw, "seed": 8})
+
+
 def test_guard_audits_then_falls_back(torch):
     from paper_2504_15508_amd import learned as L
     from paper_2504_15508_amd.plan import Plan
