@@ -1,5 +1,5 @@
 """What a correction on a 2x coarser mesh can reach: the numbers behind the
-learned coarse form's verdict, computed with the oracle only.
+learned coarse form's feasibility, computed with the oracle only.
 
 Systems: the spacing-matched training boxes (1,128 waters, 32.325 A, the
 density of the 216k system), coarse mesh 16^3 (h = 2.02 A, the spacing of 64^3
