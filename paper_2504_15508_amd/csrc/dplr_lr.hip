@@ -703,7 +703,7 @@ dplr_lr_status launch_mixed(dplr_lr_plan p, int64_t n_ion, const void* ion_pos, 
     if (fused)
       hipLaunchKernelGGL((k_mixed_spread_xy<T, P>), dim3(g.K[2], S), dim3(1024), p->mfused, s,
                          (const T4<T>*)p->mrec, (const int*)p->mspk, (const int*)p->bin_start, gs,
-                         reinterpret_cast<cpx<T>*>(p->mmesh));
+                         (const unsigned*)p->qmax, n > 0 ? nblk : 0, reinterpret_cast<cpx<T>*>(p->mmesh));
     else
       hipLaunchKernelGGL((k_mixed_spread_sorted<T, P>), dim3(g.K[2], S), dim3(1024), p->lds_mplane, s,
                          (const T4<T>*)p->mrec, (const int*)p->mspk, (const int*)p->bin_start, gs, spec, p->mmesh);

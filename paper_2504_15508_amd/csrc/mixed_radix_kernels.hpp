@@ -659,29 +659,47 @@ __device__ __forceinline__ void lds_dft_rows(cpx<T>* buf, int N, int nrows, int 
 // Plane spread (as k_mixed_spread_sorted) followed by the forward x and y
 // transforms of the plane in LDS.  Block (z, s) writes the spectrum of its
 // partial plane to part[s][z][y][x] (complex); k_mixed_fftz_poisson adds the
-// S partial spectra in split order.  The integer plane becomes complex in
-// place: every thread holds its values in registers across a barrier.
-// Block of 1024 threads; LDS (Kx Ky + Kx + Ky) complex values.
+// S partial spectra in split order.  FP32 plans take the fixed-point scale of
+// the tuned spread, 2^(30 - e) for charges below 2^e (the largest charge from
+// the sort's per-chunk maxima), so each term converts in single precision
+// (FP64 plans: 2^40).  The integer plane becomes complex in place: every
+// thread holds its values in registers across a barrier.  Block of 1024
+// threads; LDS (Kx Ky + Kx + Ky) complex values.
 template <typename T, int P>
 __global__ void __launch_bounds__(1024) k_mixed_spread_xy(const T4<T>* __restrict__ rec,
                                                           const int* __restrict__ spk,
                                                           const int* __restrict__ bin_start, Geo g,
+                                                          const unsigned* __restrict__ qmax_part, int nqpart,
                                                           cpx<T>* __restrict__ part) {
   constexpr int kMax = FusedPlane<T>::kMaxPts;
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned long long* pl = reinterpret_cast<unsigned long long*>(smem);
   cpx<T>* cp = reinterpret_cast<cpx<T>*>(smem);
   __shared__ Ranges R;
+  __shared__ unsigned qm_s;
   const int Kx = g.K[0], Ky = g.K[1], Kz = g.K[2];
   const int z = blockIdx.x, split = blockIdx.y;
   const int nxy = Kx * Ky;
   cpx<T>* twx = cp + nxy;  // beyond the integer plane as well
   cpx<T>* twy = twx + Kx;
   const RangeLoad rl = range_load(bin_start, g, split, z - (P - 1), P, 0, g.NQ);
+  unsigned qb = 0u;
+  if constexpr (sizeof(T) == 4) {
+    for (int i = threadIdx.x; i < nqpart; i += blockDim.x) qb = max(qb, qmax_part[i]);
+  }
+  if (threadIdx.x == 0) qm_s = 0u;
   for (int e = threadIdx.x; e < nxy; e += blockDim.x) pl[e] = 0ull;
   for (int m = threadIdx.x; m < Kx; m += blockDim.x) twx[m] = unit_root<T>(m, Kx, -1);
   for (int m = threadIdx.x; m < Ky; m += blockDim.x) twy[m] = unit_root<T>(m, Ky, -1);
-  ranges_finish(R, rl);  // contains barriers
+  if constexpr (sizeof(T) == 4) {
+    qb = wave_max_u32(qb);
+    __syncthreads();  // qm_s initialised
+    if ((threadIdx.x & 63) == 0 && qb) atomicMax(&qm_s, qb);
+  }
+  ranges_finish(R, rl);  // contains barriers (also publishes qm_s)
+  T scale;
+  if constexpr (sizeof(T) == 4) scale = fixed_scale_fp32(qm_s);
+  else scale = (T)kMixedFixedScale;
   const int total = R.pre[R.n];
   for (int v = threadIdx.x; v < total; v += blockDim.x) {
     const int j = range_index2(R, v);
@@ -697,7 +715,7 @@ __global__ void __launch_bounds__(1024) k_mixed_spread_xy(const T4<T>* __restric
     T wzt = wz[0];
 #pragma unroll
     for (int t = 1; t < P; ++t) wzt = (tz == t) ? wz[t] : wzt;
-    const T qz = rc.w * wzt;
+    const T qz = rc.w * scale * wzt;
     int gx[P];
 #pragma unroll
     for (int t = 0; t < P; ++t) {
@@ -711,13 +729,11 @@ __global__ void __launch_bounds__(1024) k_mixed_spread_xy(const T4<T>* __restric
       const T qyz = qz * wy[ty];
       unsigned long long* row = pl + gy * Kx;
 #pragma unroll
-      for (int tx = 0; tx < P; ++tx) {
-        const long long v2 = llrint((double)(qyz * wx[tx]) * kMixedFixedScale);
-        atomicAdd(row + gx[tx], (unsigned long long)v2);
-      }
+      for (int tx = 0; tx < P; ++tx) atomicAdd(row + gx[tx], (unsigned long long)to_fixed<T>(qyz * wx[tx]));
     }
   }
   __syncthreads();
+  const double inv_scale = 1.0 / (double)scale;
   constexpr int KV = (kMax + 1023) / 1024;
   long long held[KV];
 #pragma unroll
@@ -729,7 +745,7 @@ __global__ void __launch_bounds__(1024) k_mixed_spread_xy(const T4<T>* __restric
 #pragma unroll
   for (int j = 0; j < KV; ++j) {
     const int e = threadIdx.x + j * 1024;
-    if (e < nxy) cp[e] = cpx<T>{(T)((double)held[j] * (1.0 / kMixedFixedScale)), (T)0};
+    if (e < nxy) cp[e] = cpx<T>{(T)((double)held[j] * inv_scale), (T)0};
   }
   __syncthreads();
   lds_dft_rows<T, 1024, kMax, false>(cp, Kx, Ky, Kx, 1, false, twx);  // x rows

@@ -49,23 +49,26 @@ def test_mixed_sizes_fp64(torch_dev, mesh, order):
     check_vs_pppm(torch_dev, s, mesh, order, "fp64", 1e-9, 1e-9, 1e-9)
 
 
-@pytest.mark.parametrize("mesh", [(48, 60, 40), (72, 72, 72), (100, 64, 90)])
+# (120, 135, 10): an FP32 complex plane of 16,200 points, just under the fused
+# kernels' 16,384; (144, 120, 8): 17,280 points, just over (per-axis transforms
+# after the plane spread)
+@pytest.mark.parametrize("mesh", [(48, 60, 40), (72, 72, 72), (100, 64, 90), (120, 135, 10), (144, 120, 8)])
 def test_mixed_sizes_fp32(torch_dev, mesh):
     s = systems.workload(2).system()
     check_vs_pppm(torch_dev, s, mesh, 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_split_plane_spectra(torch_dev, precision):
+@pytest.mark.parametrize("precision,order", [("fp64", 5), ("fp32", 5), ("fp32", 8)])
+def test_split_plane_spectra(torch_dev, precision, order):
     # 68,000 charges: enough for the plane spread to split every plane's
     # particles over several blocks (Kz = 36: four splits), whose partial
     # spectra the z pass adds; odd-length y rows (45 = 3^2 5) and C = 8
     # columns per z block (Kx Ky = 1800)
     s = systems.water_box(17000, 82.0, seed=20261203, name="water17000_82A")
     if precision == "fp64":
-        check_vs_pppm(torch_dev, s, (40, 45, 36), 5, "fp64", 1e-9, 1e-9, 1e-9)
+        check_vs_pppm(torch_dev, s, (40, 45, 36), order, "fp64", 1e-9, 1e-9, 1e-9)
     else:
-        check_vs_pppm(torch_dev, s, (40, 45, 36), 5, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
+        check_vs_pppm(torch_dev, s, (40, 45, 36), order, "fp32", FP32_TOL_F, FP32_TOL_E, FP32_TOL_E)
 
 
 def test_refined_mixed_mesh_meets_ewald(torch_dev):
