@@ -28,6 +28,7 @@ constexpr int kOffMu = kNTrain, kOffIsd = kOffMu + kIn;
 constexpr int kNParams = kOffIsd + kIn;               // packed total
 constexpr int kNWeights = kIn * kH + 2 * kH * kH + kH * kOut;  // bf16 weight copy
 constexpr int kRows = 128;                            // particles per MLP block (4 waves x 32)
+constexpr int kMlpThreads = 256;                      // threads of the MLP forward and backward blocks
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -42,7 +43,9 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// silu with the hardware reciprocal (1 ulp): the result is rounded to bf16
+// before it is used, so the last FP32 bits do not matter
+__device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float dsilu(float z) {
   const float s = 1.0f / (1.0f + __expf(-z));
   return s * (1.0f + z * (1.0f - s));
@@ -511,6 +514,30 @@ __device__ __forceinline__ void mfma_tile_kc(f32x16& acc, const unsigned short* 
   }
 }
 
+// The same for two B tiles sharing A: acc0 += A B0, acc1 += A B1.
+__device__ __forceinline__ void mfma_tile_kc2(f32x16& acc0, f32x16& acc1, const unsigned short* A, int lda,
+                                              const unsigned short* B0, const unsigned short* B1, int ldb, int K) {
+  const int l = threadIdx.x & 63;
+  const int mn = l & 31, kh = (l >> 5) * 8;
+  const unsigned short* pa = A + mn * lda + kh;
+  const unsigned short* p0 = B0 + mn * ldb + kh;
+  const unsigned short* p1 = B1 + mn * ldb + kh;
+#pragma unroll 4
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bf16x4 a0 = *reinterpret_cast<const bf16x4*>(pa + k0);
+    const bf16x4 a1 = *reinterpret_cast<const bf16x4*>(pa + k0 + 4);
+    const bf16x4 b00 = *reinterpret_cast<const bf16x4*>(p0 + k0);
+    const bf16x4 b01 = *reinterpret_cast<const bf16x4*>(p0 + k0 + 4);
+    const bf16x4 b10 = *reinterpret_cast<const bf16x4*>(p1 + k0);
+    const bf16x4 b11 = *reinterpret_cast<const bf16x4*>(p1 + k0 + 4);
+    const bf16x8 a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+    const bf16x8 b0 = __builtin_shufflevector(b00, b01, 0, 1, 2, 3, 4, 5, 6, 7);
+    const bf16x8 b1 = __builtin_shufflevector(b10, b11, 0, 1, 2, 3, 4, 5, 6, 7);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+  }
+}
+
 // weight offsets in the padded LDS copies
 constexpr int kLW1t = 0, kLW2t = kLW1t + kH * kPadIn, kLW3t = kLW2t + kH * kPadH,
               kLW4t = kLW3t + kH * kPadH, kLWt = kLW4t + kOut * kPadH;  // [out][in] copies
@@ -549,17 +576,32 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restric
   extern __shared__ __align__(16) unsigned char smem[];
   FwdLds& S = *reinterpret_cast<FwdLds*>(smem);
   const int tid = threadIdx.x, wave = tid >> 6;
-  // weights: global [out][in] (dense) -> LDS rows padded
+  // weights: global [out][in] (dense) -> LDS rows padded, in 16-byte chunks
+  // of 8 values whose loads are all in flight before the first LDS store (a
+  // loop with a run-time trip count would wait for each load in turn)
   {
-    const int rows[4] = {kH, kH, kH, kOut}, cols[4] = {kIn, kH, kH, kH};
+    const int cols[4] = {kIn, kH, kH, kH};
     const int gofs[4] = {0, kIn * kH, kIn * kH + kH * kH, kIn * kH + 2 * kH * kH};
     const int lofs[4] = {kLW1t, kLW2t, kLW3t, kLW4t}, pitch[4] = {kPadIn, kPadH, kPadH, kPadH};
+    constexpr int kChunks = kNWeights / 8, kPer = (kChunks + kMlpThreads - 1) / kMlpThreads;
+    uint4 wv[kPer];
 #pragma unroll
-    for (int L = 0; L < 4; ++L)
-      for (int e = tid; e < rows[L] * cols[L]; e += blockDim.x) {
-        const int r = e / cols[L], c = e - r * cols[L];
-        S.wt[lofs[L] + r * pitch[L] + c] = wt_g[gofs[L] + e];
+    for (int u = 0; u < kPer; ++u) {
+      const int c = tid + u * kMlpThreads;
+      if (c < kChunks) wv[u] = reinterpret_cast<const uint4*>(wt_g)[c];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int c = tid + u * kMlpThreads;
+      if (c < kChunks) {
+        const int e = 8 * c;
+        const int L = e < gofs[1] ? 0 : e < gofs[2] ? 1 : e < gofs[3] ? 2 : 3;
+        const int el = e - gofs[L], r = el / cols[L], col = el - r * cols[L];
+        uint2* dst = reinterpret_cast<uint2*>(S.wt + lofs[L] + r * pitch[L] + col);  // 8-byte aligned
+        dst[0] = make_uint2(wv[u].x, wv[u].y);
+        dst[1] = make_uint2(wv[u].z, wv[u].w);
       }
+    }
   }
   for (int e = tid; e < kH; e += blockDim.x) {
     S.b[e] = params[kOffB1 + e];
@@ -574,16 +616,45 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restric
   double lsum = 0.0;
   unsigned mcorr = 0u, mforce = 0u;  // running maxima (float bits) for the guard
   const int ntiles = (n + kRows - 1) / kRows;
+  // A tile's inputs travel in 16-byte chunks held in registers: the next
+  // tile's loads are issued while the current tile computes (the block's
+  // barriers wait on LDS only, so the loads stay in flight across them).
+  constexpr int kXc = kRows * kIn / 8, kXper = kXc / kMlpThreads;
+  uint4 xv[kXper];
+  auto load_x = [&](int tile) {
+#pragma unroll
+    for (int u = 0; u < kXper; ++u) {
+      const int c = tid + u * kMlpThreads, r = c / (kIn / 8), c8 = c % (kIn / 8);
+      const int row = tile * kRows + r;
+      xv[u] = make_uint4(0u, 0u, 0u, 0u);
+      if (tile < ntiles && row < n) xv[u] = reinterpret_cast<const uint4*>(X + (size_t)row * kIn)[c8];
+    }
+  };
+  load_x(blockIdx.x);
+  // head: two threads per particle (hp = particle in the tile, hk = which
+  // half of the 32 radial orders); the particle's descriptor rows are loaded
+  // at the start of the tile, so that they arrive during the layers
+  const int hp = tid >> 1, hk = tid & 1;
+  constexpr int kHalf = kOut / 2;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int row0 = tile * kRows;
+    const bool hon = row0 + hp < n;
+    float4 tq[kHalf];
+    if (hon) {
+      const float4* Tp = reinterpret_cast<const float4*>(Tin + (size_t)(row0 + hp) * 128) + hk * kHalf;
+#pragma unroll
+      for (int k = 0; k < kHalf; ++k) tq[k] = Tp[k];
+    }
     __syncthreads();  // previous tile done with S.x / S.c; weights staged
-    for (int e = tid; e < kRows * kIn / 4; e += blockDim.x) {
-      const int r = e / (kIn / 4), c4 = e % (kIn / 4);
-      uint2 v = make_uint2(0u, 0u);
-      if (row0 + r < n) v = reinterpret_cast<const uint2*>(X + (size_t)(row0 + r) * kIn)[c4];
-      *reinterpret_cast<uint2*>(&S.x[r][4 * c4]) = v;
+#pragma unroll
+    for (int u = 0; u < kXper; ++u) {
+      const int c = tid + u * kMlpThreads, r = c / (kIn / 8), c8 = c % (kIn / 8);
+      uint2* dst = reinterpret_cast<uint2*>(&S.x[r][8 * c8]);  // 8-byte aligned rows
+      dst[0] = make_uint2(xv[u].x, xv[u].y);
+      dst[1] = make_uint2(xv[u].z, xv[u].w);
     }
     __syncthreads();
+    load_x(tile + gridDim.x);
     // hidden layers
 #pragma unroll
     for (int layer = 0; layer < 3; ++layer) {
@@ -591,11 +662,16 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restric
       const unsigned short* A = layer == 0 ? &S.x[wr][0] : &S.h[(layer - 1) & 1][wr][0];
       const int lda = layer == 0 ? kPadIn : kPadH;
       unsigned short* Hout = &S.h[layer & 1][wr][0];
+      // both 32-column tiles of the layer in one pass over k (two independent
+      // accumulation chains in flight)
+      static_assert(kH == 64, "two 32-column tiles per hidden layer");
+      f32x16 acc2[2];
+      zero(acc2[0]);
+      zero(acc2[1]);
+      mfma_tile_kc2(acc2[0], acc2[1], A, lda, wl[layer], wl[layer] + 32 * ldw[layer], ldw[layer], K);
 #pragma unroll
       for (int nt = 0; nt < kH / 32; ++nt) {
-        f32x16 acc;
-        zero(acc);
-        mfma_tile_kc(acc, A, lda, wl[layer] + nt * 32 * ldw[layer], ldw[layer], K);
+        const f32x16& acc = acc2[nt];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int row = acc_row(r), col = nt * 32 + acc_col();
@@ -621,46 +697,54 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restric
     }
     __syncthreads();
 
-    // head: one thread per particle (threads 0..127)
-    if (tid < kRows && row0 + tid < n) {
-      const int slot = row0 + tid;
-      const float* Tp = Tin + (size_t)slot * 128;
-      const float q = cpos[slot].w;
+    // head: dF = s_out q sum_k c_k T[k, 1:4], each thread over its half of k
+    // (in order), the halves added in the order (0, 1)
+    {
       float f0 = 0.f, f1 = 0.f, f2 = 0.f;
-#pragma unroll 8
-      for (int k = 0; k < kOut; ++k) {
-        const float4 t = reinterpret_cast<const float4*>(Tp)[k];
-        const float cc = S.c[tid][k];
-        f0 += cc * t.y;
-        f1 += cc * t.z;
-        f2 += cc * t.w;
+      if (hon) {
+#pragma unroll
+        for (int k = 0; k < kHalf; ++k) {
+          const float cc = S.c[hp][hk * kHalf + k];
+          f0 += cc * tq[k].y;
+          f1 += cc * tq[k].z;
+          f2 += cc * tq[k].w;
+        }
       }
-      const float sq = s_out * q;
-      f0 *= sq; f1 *= sq; f2 *= sq;
-      const int src = cidx[slot];
-      float* out = (src < n_ion) ? ion_dF + 3 * (int64_t)src : wc_dF + 3 * ((int64_t)src - n_ion);
-      mcorr = max(mcorr, __float_as_uint(sqrtf(f0 * f0 + f1 * f1 + f2 * f2)));
-      if (accumulate) {
-        mforce = max(mforce, __float_as_uint(sqrtf(out[0] * out[0] + out[1] * out[1] + out[2] * out[2])));
-        out[0] += f0; out[1] += f1; out[2] += f2;
-      } else {
-        out[0] = f0; out[1] = f1; out[2] = f2;
-      }
-      if (TRAIN) {
-        // target: the residual target - base (fine minus coarse forces) when a base is given
-        const int64_t o3 = (src < n_ion) ? 3 * (int64_t)src : 3 * ((int64_t)src - n_ion);
-        const float* tg = ((src < n_ion) ? ion_tgt : wc_tgt) + o3;
-        const float* bs = (src < n_ion) ? ion_base : wc_base;
-        float t0 = tg[0], t1 = tg[1], t2 = tg[2];
-        if (bs) { t0 -= bs[o3]; t1 -= bs[o3 + 1]; t2 -= bs[o3 + 2]; }
-        const float e0 = f0 - t0, e1 = f1 - t1, e2 = f2 - t2;
-        lsum += (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
-        // dL/d dF = gscale * e (gscale = 2 / (3 n)); dL/dc_k = s_out q (g . T[k, 1:4])
-        const float g0 = gscale * e0 * sq, g1 = gscale * e1 * sq, g2 = gscale * e2 * sq;
-#pragma unroll 8
-        for (int k = 0; k < kOut; ++k) {
-          const float4 t = reinterpret_cast<const float4*>(Tp)[k];
-          dC[(size_t)slot * kOut + k] = g0 * t.y + g1 * t.z + g2 * t.w;
+      const float o0 = __shfl_xor(f0, 1, 64), o1 = __shfl_xor(f1, 1, 64), o2 = __shfl_xor(f2, 1, 64);
+      // both threads of the pair form the same sums: half 0 first
+      f0 = hk == 0 ? f0 + o0 : o0 + f0;
+      f1 = hk == 0 ? f1 + o1 : o1 + f1;
+      f2 = hk == 0 ? f2 + o2 : o2 + f2;
+      if (hon) {
+        const int slot = row0 + hp;
+        const float q = cpos[slot].w;
+        const float sq = s_out * q;
+        f0 *= sq; f1 *= sq; f2 *= sq;
+        const int src = cidx[slot];
+        float* out = (src < n_ion) ? ion_dF + 3 * (int64_t)src : wc_dF + 3 * ((int64_t)src - n_ion);
+        if (hk == 0) {
+          mcorr = max(mcorr, __float_as_uint(sqrtf(f0 * f0 + f1 * f1 + f2 * f2)));
+          if (accumulate) {
+            mforce = max(mforce, __float_as_uint(sqrtf(out[0] * out[0] + out[1] * out[1] + out[2] * out[2])));
+            out[0] += f0; out[1] += f1; out[2] += f2;
+          } else {
+            out[0] = f0; out[1] = f1; out[2] = f2;
+          }
+        }
+        if (TRAIN) {
+          // target: the residual target - base (fine minus coarse forces) when a base is given
+          const int64_t o3 = (src < n_ion) ? 3 * (int64_t)src : 3 * ((int64_t)src - n_ion);
+          const float* tg = ((src < n_ion) ? ion_tgt : wc_tgt) + o3;
+          const float* bs = (src < n_ion) ? ion_base : wc_base;
+          float t0 = tg[0], t1 = tg[1], t2 = tg[2];
+          if (bs) { t0 -= bs[o3]; t1 -= bs[o3 + 1]; t2 -= bs[o3 + 2]; }
+          const float e0 = f0 - t0, e1 = f1 - t1, e2 = f2 - t2;
+          if (hk == 0) lsum += (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
+          // dL/d dF = gscale * e (gscale = 2 / (3 n)); dL/dc_k = s_out q (g . T[k, 1:4])
+          const float g0 = gscale * e0 * sq, g1 = gscale * e1 * sq, g2 = gscale * e2 * sq;
+#pragma unroll
+          for (int k = 0; k < kHalf; ++k)
+            dC[(size_t)slot * kOut + hk * kHalf + k] = g0 * tq[k].y + g1 * tq[k].z + g2 * tq[k].w;
         }
       }
     }
@@ -674,7 +758,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const unsigned short* __restric
     }
   }
   if (TRAIN) {
-    // deterministic block sum of the squared errors (threads 0..127 hold them)
+    // deterministic block sum of the squared errors (the even threads hold them)
     for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
     __syncthreads();
     if ((tid & 63) == 0) S.lred[wave] = lsum;
