@@ -19,8 +19,10 @@
  * Conventions
  *   - Units: Angstrom, elementary charge, eV (k_e = 14.399645 eV A gives eV).
  *   - Box: orthorhombic, edge lengths L[3]; positions may lie anywhere (they
- *     are wrapped into the box).  The m = 0 term is excluded (tin-foil
- *     boundary); a non-neutral input is computed as given.
+ *     are wrapped into the box).  A non-finite coordinate (NaN or +-Inf) is
+ *     taken as 0 on its axis, so no input position leads outside the mesh;
+ *     non-finite charges give non-finite outputs.  The m = 0 term is excluded
+ *     (tin-foil boundary); a non-neutral input is computed as given.
  *   - Arrays: positions and forces are contiguous [n][3] (x, y, z), charges
  *     [n]; element type float for DPLR_LR_FP32 plans and double for
  *     DPLR_LR_FP64 plans.  Energy and virial are always double.

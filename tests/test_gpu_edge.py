@@ -156,6 +156,30 @@ def test_repeated_calls_with_shrinking_input(torch, dl):
         assert np.linalg.norm(F - F0) <= 1e-10 * np.linalg.norm(F0)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("mesh", [32, (12, 18, 12)])
+def test_non_finite_coordinates_count_as_zero(torch, dl, precision, mesh):
+    """A NaN or infinite coordinate is taken as 0 on its axis (documented in
+    the header): the step runs, and its results are those of the same input
+    with 0 in place of each non-finite coordinate, bit for bit."""
+    s = systems.workload(1).system()
+    K = (mesh,) * 3 if isinstance(mesh, int) else mesh
+    p = _plan(dl, mesh=K, precision=precision, capacity=s.n, box=tuple(s.box))
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    bad_i, bad_w = s.ion_pos.copy(), s.wc_pos.copy()
+    bad_i[3] = [np.nan, bad_i[3, 1], bad_i[3, 2]]
+    bad_i[7] = [np.inf, -np.inf, np.nan]
+    bad_w[2] = [bad_w[2, 0], -np.inf, bad_w[2, 2]]
+    fix_i, fix_w = np.where(np.isfinite(bad_i), bad_i, 0.0), np.where(np.isfinite(bad_w), bad_w, 0.0)
+    iq, wq = _t(torch, s.ion_q, dt), _t(torch, s.wc_q, dt)
+    E1, fi1, fw1, W1 = [x.clone() for x in p.compute(_t(torch, bad_i, dt), iq, _t(torch, bad_w, dt), wq)]
+    E2, fi2, fw2, W2 = p.compute(_t(torch, fix_i, dt), iq, _t(torch, fix_w, dt), wq)
+    torch.cuda.synchronize()
+    assert torch.isfinite(fi1).all() and torch.isfinite(fw1).all() and bool(torch.isfinite(E1))
+    assert torch.equal(fi1, fi2) and torch.equal(fw1, fw2)
+    assert torch.equal(E1, E2) and torch.equal(W1, W2)
+
+
 def test_fp32_is_bitwise_repeatable(torch, dl):
     """The charge mesh is summed in integers (order-independent), every force
     is accumulated by one thread in a fixed order and the FP64 reductions use
