@@ -349,7 +349,7 @@ __global__ void __launch_bounds__(128) k_norm_finish(double* __restrict__ acc, f
 // together (candidate jb + g), and the ones inside the cutoff are appended to
 // the particle's LDS list in candidate order (ballot + prefix count, so the
 // order is deterministic); then every lane accumulates its orders over the
-// whole list.  Writes T [n][128] (FP32, index 4k + a) and the normalised MLP
+// whole list, the pair quantities formed once per pair (accumulate_pairs).  Writes T [n][128] (FP32, index 4k + a) and the normalised MLP
 // input x [n][128] (bf16).
 // ---------------------------------------------------------------------------
 constexpr int kDescLanes = 4;
@@ -357,39 +357,56 @@ constexpr int kDescThreads = 256;
 constexpr int kDescParts = kDescThreads / kDescLanes;
 constexpr int kNbrMax = 64;
 
+// Pairs per round of the accumulation: the four lanes of a particle form the
+// round's pair quantities (weight, unit vector, Chebyshev argument) once, one
+// pair each in turn, through the particle's LDS slots, and then every lane
+// runs its eight orders over all of them.
+constexpr int kPairChunk = 8;  // 4 measured the same, 16 slower (LDS per block)
+
 __device__ __forceinline__ void accumulate_pairs(float (&T)[8][4], const float4 pi, const float4* __restrict__ cpos,
-                                                 const int* list, int cnt, int g, const CellGeo& c) {
+                                                 const int* list, int cnt, int g, const CellGeo& c,
+                                                 float (*pq)[5]) {
   const float inv_rc = 1.0f / c.rc;
-  for (int t = 0; t < cnt; ++t) {
-    const float4 pj = cpos[list[t]];
-    float d0 = pj.x - pi.x, d1 = pj.y - pi.y, d2 = pj.z - pi.z;
-    d0 -= c.L[0] * rintf(d0 * c.invL[0]);
-    d1 -= c.L[1] * rintf(d1 * c.invL[1]);
-    d2 -= c.L[2] * rintf(d2 * c.invL[2]);
-    const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    const float r = sqrtf(r2), ir = 1.0f / r;
-    const float sw = 0.5f * (1.0f + __cosf(3.14159265358979f * r * inv_rc));
-    const float x = 2.0f * r * inv_rc - 1.0f;
-    const float w = pj.w * sw;
-    const float u1 = d0 * ir, u2 = d1 * ir, u3 = d2 * ir;
-    const float t2 = 2.0f * x * x - 1.0f, t3 = 2.0f * x * t2 - x, t4 = 2.0f * x * t3 - t2;
-    // lane g starts from T_g and T_{4-g}
-    float cur = (g == 0) ? 1.0f : (g == 1) ? x : (g == 2) ? t2 : t3;
-    float prev = (g == 0) ? t4 : (g == 1) ? t3 : (g == 2) ? t2 : x;
-    const float t4x2 = 2.0f * t4;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      if (m > 0) {
-        const float nxt = t4x2 * cur - prev;
-        prev = cur;
-        cur = nxt;
-      }
-      const float wg = w * cur;
-      T[m][0] += wg;
-      T[m][1] += wg * u1;
-      T[m][2] += wg * u2;
-      T[m][3] += wg * u3;
+  for (int t0 = 0; t0 < cnt; t0 += kPairChunk) {
+    const int nc = min(kPairChunk, cnt - t0);
+    for (int t = g; t < nc; t += kDescLanes) {
+      const float4 pj = cpos[list[t0 + t]];
+      float d0 = pj.x - pi.x, d1 = pj.y - pi.y, d2 = pj.z - pi.z;
+      d0 -= c.L[0] * rintf(d0 * c.invL[0]);
+      d1 -= c.L[1] * rintf(d1 * c.invL[1]);
+      d2 -= c.L[2] * rintf(d2 * c.invL[2]);
+      const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const float r = sqrtf(r2), ir = 1.0f / r;
+      const float sw = 0.5f * (1.0f + __cosf(3.14159265358979f * r * inv_rc));
+      pq[t][0] = pj.w * sw;
+      pq[t][1] = d0 * ir;
+      pq[t][2] = d1 * ir;
+      pq[t][3] = d2 * ir;
+      pq[t][4] = 2.0f * r * inv_rc - 1.0f;
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the round's slots written
+    for (int t = 0; t < nc; ++t) {
+      const float w = pq[t][0], u1 = pq[t][1], u2 = pq[t][2], u3 = pq[t][3], x = pq[t][4];
+      const float t2 = 2.0f * x * x - 1.0f, t3 = 2.0f * x * t2 - x, t4 = 2.0f * x * t3 - t2;
+      // lane g starts from T_g and T_{4-g}
+      float cur = (g == 0) ? 1.0f : (g == 1) ? x : (g == 2) ? t2 : t3;
+      float prev = (g == 0) ? t4 : (g == 1) ? t3 : (g == 2) ? t2 : x;
+      const float t4x2 = 2.0f * t4;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        if (m > 0) {
+          const float nxt = t4x2 * cur - prev;
+          prev = cur;
+          cur = nxt;
+        }
+        const float wg = w * cur;
+        T[m][0] += wg;
+        T[m][1] += wg * u1;
+        T[m][2] += wg * u2;
+        T[m][3] += wg * u3;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // all four lanes done before the next round
   }
 }
 
@@ -400,6 +417,7 @@ __global__ void __launch_bounds__(kDescThreads) k_descriptor(const float4* __res
                                                              unsigned short* __restrict__ X, CellGeo c,
                                                              int* __restrict__ nbr) {
   __shared__ int lists[kDescParts][kNbrMax];
+  __shared__ float pqs[kDescParts][kPairChunk][5];
   const int g = threadIdx.x & (kDescLanes - 1), p = threadIdx.x / kDescLanes;
   const int lane = threadIdx.x & 63, gbase = lane & ~(kDescLanes - 1);
   const int i = blockIdx.x * kDescParts + p;
@@ -443,7 +461,7 @@ __global__ void __launch_bounds__(kDescThreads) k_descriptor(const float4* __res
           total += __popc(gm);
           if (cnt > kNbrMax - kDescLanes) {  // the same decision on all four lanes
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            accumulate_pairs(T, pi, cpos, list, cnt, g, c);
+            accumulate_pairs(T, pi, cpos, list, cnt, g, c, pqs[p]);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             cnt = 0;
           }
@@ -452,7 +470,7 @@ __global__ void __launch_bounds__(kDescThreads) k_descriptor(const float4* __res
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  accumulate_pairs(T, pi, cpos, list, cnt, g, c);
+  accumulate_pairs(T, pi, cpos, list, cnt, g, c, pqs[p]);
   if (nbr && g == 0) nbr[i] = total;  // neighbour count, reduced by k_nbr_range
   float* to = Tout + (size_t)i * 128;
 #pragma unroll
